@@ -1,0 +1,175 @@
+"""CPU oracle for the RBSM / RSMSS per-fragment shadow pass (arXiv 1711.07793).
+
+TEST INFRASTRUCTURE.  Only the test suite, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg may import this package.  The product library
+(``paper_1711_07793_amd``) never imports, links or calls it, and the two share
+no code.
+
+The arithmetic lives in ``rbsm_oracle.c`` (plain single-threaded C, binary32 in
+the paper's listing order, built with ``-ffp-contract=off``); this module only
+marshals numpy arrays through ctypes.  A second, independently structured
+implementation (``stencil.py``, whole-map numpy array operations) exists only to
+cross-check the C oracle on exhaustive tiny maps.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "librbsm_oracle.so")
+_lib = None
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pitch", ctypes.c_int64),
+                ("depth_bias", ctypes.c_float), ("max_dist", ctypes.c_int32),
+                ("kernel_radius", ctypes.c_int32)]
+
+
+class Detail(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_float), ("d", ctypes.c_float * 3), ("rd", ctypes.c_int32 * 4),
+                ("nrd", ctypes.c_float * 4), ("path", ctypes.c_int32), ("vis", ctypes.c_float)]
+
+
+def build() -> str:
+    """Compile the oracle with gcc (binary32, no FMA contraction, no fast-math)."""
+    src = os.path.join(_HERE, "rbsm_oracle.c")
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", _LIB_PATH, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    global _lib
+    _lib = None
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    P = ctypes.POINTER(_Params)
+    for name in ("oracle_shadow_map", "oracle_rbsm_hard", "oracle_rsmss"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp, vp, i64, P, vp]
+        fn.restype = ctypes.c_int
+    lib.oracle_detail_one.argtypes = [vp, vp, P, ctypes.c_int, ctypes.POINTER(Detail)]
+    lib.oracle_detail_one.restype = ctypes.c_int
+    lib.oracle_multi.argtypes = [vp, i64, vp, vp, i64, P, ctypes.c_int, vp, vp, vp]
+    lib.oracle_multi.restype = ctypes.c_int
+    lib.oracle_margin_one.argtypes = [vp, vp, P, ctypes.c_int]
+    lib.oracle_margin_one.restype = ctypes.c_double
+    lib.oracle_set_touch.argtypes = [vp]
+    lib.oracle_set_touch.restype = None
+    lib.oracle_fetch_count.argtypes = []
+    lib.oracle_fetch_count.restype = ctypes.c_int64
+    _lib = lib
+    return lib
+
+
+def _params(p: dict) -> _Params:
+    return _Params(int(p["width"]), int(p["height"]), int(p.get("pitch", p["width"])),
+                   float(p.get("depth_bias", 0.0)), int(p.get("max_dist", 16)),
+                   int(p.get("kernel_radius", 0)))
+
+
+def _c(a: np.ndarray, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise ValueError(f"{what}: oracle rejected the input (status {st})")
+
+
+def shadow_map(map_: np.ndarray, frags: np.ndarray, params: dict) -> np.ndarray:
+    """Plain shadow mapping, Eq. 1: uint8 [N], 0 = shadow, 1 = lit."""
+    m, f = _c(map_, np.float32), _c(frags, np.float32).reshape(-1, 3)
+    out = np.empty(f.shape[0], dtype=np.uint8)
+    p = _params(params)
+    _check(_load().oracle_shadow_map(m.ctypes.data, f.ctypes.data, f.shape[0], ctypes.byref(p),
+                                     out.ctypes.data), "shadow_map")
+    return out
+
+
+def rbsm_hard(map_: np.ndarray, frags: np.ndarray, params: dict) -> np.ndarray:
+    """Hard RBSM (silhouette recovery, Listings 1-4): uint8 [N], 0 = shadow, 1 = lit."""
+    m, f = _c(map_, np.float32), _c(frags, np.float32).reshape(-1, 3)
+    out = np.empty(f.shape[0], dtype=np.uint8)
+    p = _params(params)
+    _check(_load().oracle_rbsm_hard(m.ctypes.data, f.ctypes.data, f.shape[0], ctypes.byref(p),
+                                    out.ctypes.data), "rbsm_hard")
+    return out
+
+
+def rsmss(map_: np.ndarray, frags: np.ndarray, params: dict) -> np.ndarray:
+    """RSMSS (filtering, Listings 1-3 and 5), RPCF box average when kernel_radius > 0: float32 [N]."""
+    m, f = _c(map_, np.float32), _c(frags, np.float32).reshape(-1, 3)
+    out = np.empty(f.shape[0], dtype=np.float32)
+    p = _params(params)
+    _check(_load().oracle_rsmss(m.ctypes.data, f.ctypes.data, f.shape[0], ctypes.byref(p),
+                                out.ctypes.data), "rsmss")
+    return out
+
+
+def detail(map_: np.ndarray, frag, params: dict, hard: bool) -> Detail:
+    """All intermediate values of one fragment (s, d, rd, nrd, path, vis)."""
+    m = _c(map_, np.float32)
+    f = _c(np.asarray(frag, dtype=np.float32).reshape(3), np.float32)
+    out = Detail()
+    p = _params(params)
+    _check(_load().oracle_detail_one(m.ctypes.data, f.ctypes.data, ctypes.byref(p), 1 if hard else 0,
+                                     ctypes.byref(out)), "detail")
+    return out
+
+
+def multi(maps: np.ndarray, map_index: np.ndarray, frags: np.ndarray, params: dict, hard: bool):
+    """Evaluate fragment k on map ``maps[map_index[k]]`` (a stack of equal maps).
+
+    Returns (vis float32 [N], rd int32 [N, 4], nrd float32 [N, 4])."""
+    ms = _c(maps, np.float32)
+    stride = ms.shape[1] * ms.shape[2]
+    idx = _c(map_index, np.int32)
+    f = _c(frags, np.float32).reshape(-1, 3)
+    n = f.shape[0]
+    vis = np.empty(n, np.float32)
+    rd = np.empty((n, 4), np.int32)
+    nrd = np.empty((n, 4), np.float32)
+    p = _params(params)
+    _check(_load().oracle_multi(ms.ctypes.data, stride, idx.ctypes.data, f.ctypes.data, n,
+                                ctypes.byref(p), 1 if hard else 0, vis.ctypes.data, rd.ctypes.data,
+                                nrd.ctypes.data), "multi")
+    return vis, rd, nrd
+
+
+def margin(map_: np.ndarray, frag, params: dict, hard: bool) -> float:
+    """Binary64 distance of one fragment to its nearest decision boundary."""
+    m = _c(map_, np.float32)
+    f = _c(np.asarray(frag, dtype=np.float32).reshape(3), np.float32)
+    p = _params(params)
+    return float(_load().oracle_margin_one(m.ctypes.data, f.ctypes.data, ctypes.byref(p), 1 if hard else 0))
+
+
+def touched_texels(map_: np.ndarray, frags: np.ndarray, params: dict, hard: bool):
+    """Run the pass with read instrumentation.
+
+    Returns (touch uint8 [H, W] marking every texel read, number of reads)."""
+    H, W = int(params["height"]), int(params["width"])
+    touch = np.zeros((H, W), np.uint8)
+    lib = _load()
+    lib.oracle_set_touch(touch.ctypes.data)
+    try:
+        if hard:
+            rbsm_hard(map_, frags, params)
+        else:
+            rsmss(map_, frags, params)
+        reads = int(lib.oracle_fetch_count())
+    finally:
+        lib.oracle_set_touch(None)
+    return touch, reads

@@ -1,0 +1,388 @@
+/*
+ * CPU oracle for revectorization-based shadow mapping (RBSM): hard silhouette
+ * recovery and the filtered variant (RSMSS), from Macedo, Apolinario, Aguero,
+ * "Optimized Visibility Functions for Revectorization-Based Shadow Mapping"
+ * (arXiv 1711.07793).
+ *
+ * TEST INFRASTRUCTURE.  This file is the slow, plain reference the GPU path is
+ * checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the product library never does.  It shares no
+ * code, header or constant with the GPU path.
+ *
+ * Precision: the paper's listings compute in GLSL float, so the oracle computes
+ * in IEEE binary32 in the order the listings write, built without FMA
+ * contraction (-ffp-contract=off) and without -ffast-math.  Binary64 appears
+ * only in the decision-margin helper used to confirm that a disagreement sits
+ * on a decision boundary.
+ *
+ * Readings of points the paper leaves open (each also recorded in the design
+ * notes):
+ *  - nearest-texel addressing: X = u*W, texel floor(X), sub-texel fraction
+ *    X - floor(X); every texel index is clamped to the map (clamp-to-edge);
+ *  - the depth test is Eq. 1 with a caller bias: lit unless (z - bias) > T,
+ *    with z - bias rounded to binary32 once;
+ *  - neighbour and traversal steps move by whole texels;
+ *  - checkDiscontinuity (called but not defined in the traversal listing) is
+ *    true when the visited texel, tested at the fragment's own depth, has a
+ *    discontinuity in at least one direction in which the fragment has one
+ *    (Sec. 3.1.3, "share at least one discontinuity direction");
+ *  - computeFragmentDistanceToSE walks left, right, top (+y), bottom (-y);
+ *  - normalizeFragmentDistanceToSE: per axis, count the walks that found an
+ *    end (Eq. 5 code: 2 -> 1, 1 -> 0, 0 -> -1).  With one end, the
+ *    normalized distance is the distance from the fragment to the boundary of
+ *    the end texel divided by the number of edge texels on that axis
+ *    (|rd-| + |rd+| - 1); with no end it is 1, with two ends 0;
+ *  - the RSMSS I-shape test reads nrd.w == -1 (the printed "nrd.w == 1.0" is
+ *    unreachable there);
+ *  - RPCF (radius r > 0): box average of the RSMSS value evaluated at the
+ *    (2r+1)^2 texels around the fragment's texel with the same sub-texel
+ *    position and depth (Sec. 5.3 suggests PCF to suppress skeleton artifacts).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t width, height;
+    int64_t pitch;
+    float depth_bias;
+    int32_t max_dist;
+    int32_t kernel_radius;
+} oracle_params;
+
+/* Optional instrumentation: when non-null every texel read is marked here
+ * (row-major, width*height bytes) and counted. */
+static uint8_t *g_touch = NULL;
+static int64_t g_fetches = 0;
+
+void oracle_set_touch(uint8_t *touch) {
+    g_touch = touch;
+    g_fetches = 0;
+}
+int64_t oracle_fetch_count(void) { return g_fetches; }
+
+/* texture2D(SM, ...).z with nearest filtering and clamp-to-edge */
+static float fetch(const float *map, const oracle_params *p, int i, int j) {
+    if (i < 0) i = 0;
+    if (i > p->width - 1) i = p->width - 1;
+    if (j < 0) j = 0;
+    if (j > p->height - 1) j = p->height - 1;
+    if (g_touch) {
+        g_touch[(int64_t)j * p->width + i] = 1;
+        ++g_fetches;
+    }
+    return map[(int64_t)j * p->pitch + i];
+}
+
+/* Eq. 1: s = 0 if p_z > z(t), 1 otherwise (pz already carries the bias). */
+static float shadow_test(float pz, float blocker) { return pz > blocker ? 0.0f : 1.0f; }
+
+/* Eq. 2 / computeN: tests of the 4-connected neighbours at the same depth,
+ * in the order left, right, top (+y), bottom (-y). */
+static void compute_N(const float *map, const oracle_params *p, int i, int j, float pz, float N[4]) {
+    N[0] = shadow_test(pz, fetch(map, p, i - 1, j));
+    N[1] = shadow_test(pz, fetch(map, p, i + 1, j));
+    N[2] = shadow_test(pz, fetch(map, p, i, j + 1));
+    N[3] = shadow_test(pz, fetch(map, p, i, j - 1));
+}
+
+/* Eq. 3: uncompressed discontinuity |N - s|. */
+static void discontinuity_dirs(const float *map, const oracle_params *p, int i, int j, float pz,
+                               float s, float dU[4]) {
+    float N[4];
+    compute_N(map, p, i, j, pz, N);
+    for (int k = 0; k < 4; ++k) dU[k] = fabsf(N[k] - s);
+}
+
+/* Eq. 4: compressed discontinuity d = ((2 dL + dR)/4, (2 dT + dB)/4, 1 - s). */
+static void compress_discontinuity(const float dU[4], float s, float d[3]) {
+    d[0] = (2.0f * dU[0] + dU[1]) / 4.0f;
+    d[1] = (2.0f * dU[2] + dU[3]) / 4.0f;
+    d[2] = 1.0f - s;
+}
+
+/* Do the visited texel and the fragment share a discontinuity direction? */
+static int check_discontinuity(const float *map, const oracle_params *p, int i, int j, float pz,
+                               float s, const float dU0[4]) {
+    float dU[4];
+    discontinuity_dirs(map, p, i, j, pz, s, dU);
+    for (int k = 0; k < 4; ++k)
+        if (dU0[k] == 1.0f && dU[k] == 1.0f) return 1;
+    return 0;
+}
+
+/* traverseShadowSilhouette: walk at most max_dist texels in (dx, dy).  The
+ * distance starts at 1 and grows by one per step that stays on the edge; it
+ * is returned positive when an end (a texel with the opposite test) was found
+ * and negative otherwise. */
+static int traverse(const float *map, const oracle_params *p, int i0, int j0, float pz, float s,
+                    const float dU0[4], int dx, int dy) {
+    float shadow_edge_end = 0.0f;
+    int distance = 1;
+    int i = i0, j = j0;
+    for (int it = 0; it < p->max_dist; ++it) {
+        i += dx;
+        j += dy;
+        const float snp = shadow_test(pz, fetch(map, p, i, j));
+        if (snp != s) {
+            shadow_edge_end = 1.0f;
+            break;
+        }
+        if (!check_discontinuity(map, p, i, j, pz, s, dU0)) break;
+        distance++;
+    }
+    return shadow_edge_end == 1.0f ? distance : -distance;
+}
+
+/* normalizeFragmentDistanceToSE for one axis (Eq. 5 and Sec. 3.1.4). */
+static void normalize_axis(int rd_neg, int rd_pos, float f, float *nrd, float *code) {
+    const int ends = (rd_neg > 0) + (rd_pos > 0);
+    if (ends == 2) {
+        *code = 1.0f;
+        *nrd = 0.0f;
+    } else if (ends == 0) {
+        *code = -1.0f;
+        *nrd = 1.0f;
+    } else {
+        *code = 0.0f;
+        const int an = rd_neg < 0 ? -rd_neg : rd_neg;
+        const int ap = rd_pos < 0 ? -rd_pos : rd_pos;
+        const float len = (float)(an + ap - 1);
+        const float a = rd_pos > 0 ? (float)rd_pos - f : (float)(an - 1) + f;
+        *nrd = a / len;
+    }
+}
+
+/* Listing 4: silhouette recovery visibility. */
+static float smsr_visibility(const float d[3], const float nrd[4]) {
+    if (d[0] == 0.75f || d[1] == 0.75f) return 0.0f;
+    if (nrd[2] == 1.0f || nrd[3] == 1.0f) return 0.0f;
+    if (nrd[2] == -1.0f || nrd[3] == -1.0f) return 1.0f;
+    const float edge = 1.0f - nrd[0];
+    return nrd[1] < edge ? 0.0f : 1.0f; /* step(1 - nrd.x, nrd.y) */
+}
+
+static float clamp01(float x) {
+    const float lo = x > 0.0f ? x : 0.0f;
+    return lo < 1.0f ? lo : 1.0f;
+}
+
+/* Listing 5: filtering visibility. */
+static float rsmss_visibility_fn(const float d[3], const float nrd[4]) {
+    const float sign = -2.0f * d[2] + 1.0f;
+    if (d[0] == 0.75f && d[1] == 0.75f) return d[2];
+    if (nrd[2] == 1.0f && nrd[3] == 1.0f) return d[2];
+    if (nrd[2] == 1.0f) return d[2] + sign * nrd[1];
+    if (nrd[3] == 1.0f) return d[2] + sign * nrd[0];
+    if (nrd[2] == -1.0f || nrd[3] == -1.0f) return 1.0f - d[2];
+    const float t = d[2] + sign * nrd[1];
+    return clamp01(t + sign * nrd[0]);
+}
+
+/* Everything the pass computes for one fragment at texel (i0, j0). */
+typedef struct {
+    float s;        /* centre test */
+    float d[3];     /* compressed discontinuity */
+    int32_t rd[4];  /* left, right, top, bottom; 0 when not traversed */
+    float nrd[4];   /* normalized distances (x, y) and codes (z, w) */
+    int32_t path;   /* 0 early shadow exit (hard), 1 no discontinuity, 2 revectorized */
+    float vis;
+} oracle_detail;
+
+/* The RBSM listing for one fragment whose texel is (i0, j0), sub-texel
+ * position (fx, fy), depth pz (bias applied). hard != 0 selects silhouette
+ * recovery, else filtering. */
+static void rbsm_at(const float *map, const oracle_params *p, int i0, int j0, float fx, float fy,
+                    float pz, int hard, oracle_detail *out) {
+    memset(out, 0, sizeof(*out));
+    const float z = fetch(map, p, i0, j0);
+    const float s = shadow_test(pz, z);
+    out->s = s;
+    if (hard && s == 0.0f) {
+        out->path = 0;
+        out->vis = s;
+        return;
+    }
+    float dU[4];
+    discontinuity_dirs(map, p, i0, j0, pz, s, dU);
+    compress_discontinuity(dU, s, out->d);
+    if (!(out->d[0] > 0.0f || out->d[1] > 0.0f)) {
+        out->path = 1;
+        out->vis = s;
+        return;
+    }
+    /* computeFragmentDistanceToSE: left, right, top, bottom */
+    out->rd[0] = traverse(map, p, i0, j0, pz, s, dU, -1, 0);
+    out->rd[1] = traverse(map, p, i0, j0, pz, s, dU, +1, 0);
+    out->rd[2] = traverse(map, p, i0, j0, pz, s, dU, 0, +1);
+    out->rd[3] = traverse(map, p, i0, j0, pz, s, dU, 0, -1);
+    normalize_axis(out->rd[0], out->rd[1], fx, &out->nrd[0], &out->nrd[2]);
+    normalize_axis(out->rd[3], out->rd[2], fy, &out->nrd[1], &out->nrd[3]);
+    out->path = 2;
+    out->vis = hard ? smsr_visibility(out->d, out->nrd) : rsmss_visibility_fn(out->d, out->nrd);
+}
+
+/* Fragment addressing: texel and sub-texel fraction from (u, v). */
+static void address(const oracle_params *p, const float *frag, int *i0, int *j0, float *fx,
+                    float *fy, float *pz) {
+    const float X = frag[0] * (float)p->width;
+    const float Y = frag[1] * (float)p->height;
+    const float flx = floorf(X), fly = floorf(Y);
+    *i0 = (int)flx;
+    *j0 = (int)fly;
+    *fx = X - flx;
+    *fy = Y - fly;
+    *pz = frag[2] - p->depth_bias;
+}
+
+static int params_ok(const oracle_params *p) {
+    return p && p->width >= 1 && p->height >= 1 && p->pitch >= p->width && p->max_dist >= 1 &&
+           p->kernel_radius >= 0;
+}
+
+/* Fragments must be finite with |u*W|, |v*H| < 2^20 (the oracle does not
+ * extend addressing beyond that range). */
+static int frag_ok(const oracle_params *p, const float *f) {
+    if (!isfinite(f[0]) || !isfinite(f[1]) || !isfinite(f[2])) return 0;
+    return fabsf(f[0] * (float)p->width) < 1048576.0f && fabsf(f[1] * (float)p->height) < 1048576.0f;
+}
+
+/* Plain shadow mapping (Eq. 1 only). out: 0 shadow, 1 lit. */
+int oracle_shadow_map(const float *map, const float *frags, int64_t n, const oracle_params *p,
+                      uint8_t *out) {
+    if (!params_ok(p)) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        const float *f = frags + 3 * k;
+        if (!frag_ok(p, f)) return -2;
+        int i0, j0;
+        float fx, fy, pz;
+        address(p, f, &i0, &j0, &fx, &fy, &pz);
+        out[k] = (uint8_t)shadow_test(pz, fetch(map, p, i0, j0));
+    }
+    return 0;
+}
+
+/* Hard RBSM (silhouette recovery). out: 0 shadow, 1 lit. */
+int oracle_rbsm_hard(const float *map, const float *frags, int64_t n, const oracle_params *p,
+                     uint8_t *out) {
+    if (!params_ok(p) || p->kernel_radius != 0) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        const float *f = frags + 3 * k;
+        if (!frag_ok(p, f)) return -2;
+        int i0, j0;
+        float fx, fy, pz;
+        address(p, f, &i0, &j0, &fx, &fy, &pz);
+        oracle_detail det;
+        rbsm_at(map, p, i0, j0, fx, fy, pz, 1, &det);
+        out[k] = (uint8_t)det.vis;
+    }
+    return 0;
+}
+
+/* RSMSS (filtered); with kernel_radius r > 0, the RPCF box average. */
+int oracle_rsmss(const float *map, const float *frags, int64_t n, const oracle_params *p,
+                 float *out) {
+    if (!params_ok(p)) return -1;
+    const int r = p->kernel_radius;
+    const float inv = 1.0f / (float)((2 * r + 1) * (2 * r + 1));
+    for (int64_t k = 0; k < n; ++k) {
+        const float *f = frags + 3 * k;
+        if (!frag_ok(p, f)) return -2;
+        int i0, j0;
+        float fx, fy, pz;
+        address(p, f, &i0, &j0, &fx, &fy, &pz);
+        oracle_detail det;
+        if (r == 0) {
+            rbsm_at(map, p, i0, j0, fx, fy, pz, 0, &det);
+            out[k] = det.vis;
+            continue;
+        }
+        float sum = 0.0f;
+        for (int a = -r; a <= r; ++a)
+            for (int b = -r; b <= r; ++b) {
+                rbsm_at(map, p, i0 + a, j0 + b, fx, fy, pz, 0, &det);
+                sum += det.vis;
+            }
+        out[k] = sum * inv;
+    }
+    return 0;
+}
+
+/* Per-fragment intermediate values, for tests.  hard selects the variant. */
+int oracle_detail_one(const float *map, const float *frag, const oracle_params *p, int hard,
+                      oracle_detail *out) {
+    if (!params_ok(p) || !frag_ok(p, frag)) return -1;
+    int i0, j0;
+    float fx, fy, pz;
+    address(p, frag, &i0, &j0, &fx, &fy, &pz);
+    rbsm_at(map, p, i0, j0, fx, fy, pz, hard, out);
+    return 0;
+}
+
+/* Batched helper for tiny-map enumeration: fragment k reads map number
+ * map_index[k] from a stack of equally sized maps (map_stride floats apart). */
+int oracle_multi(const float *maps, int64_t map_stride, const int32_t *map_index,
+                 const float *frags, int64_t n, const oracle_params *p, int hard, float *vis,
+                 int32_t *rd_out, float *nrd_out) {
+    if (!params_ok(p)) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        const float *f = frags + 3 * k;
+        if (!frag_ok(p, f)) return -2;
+        int i0, j0;
+        float fx, fy, pz;
+        address(p, f, &i0, &j0, &fx, &fy, &pz);
+        oracle_detail det;
+        rbsm_at(maps + (int64_t)map_index[k] * map_stride, p, i0, j0, fx, fy, pz, hard, &det);
+        vis[k] = det.vis;
+        if (rd_out) memcpy(rd_out + 4 * k, det.rd, sizeof(det.rd));
+        if (nrd_out) memcpy(nrd_out + 4 * k, det.nrd, sizeof(det.nrd));
+    }
+    return 0;
+}
+
+/* Binary64 decision margin of one fragment: the smallest distance to a
+ * decision boundary over the depth tests the pass performs, and, for a
+ * revectorized fragment, over the L-line test |nrd.y - (1 - nrd.x)| and the
+ * RSMSS clamp, all recomputed in binary64 from the same integer walk.
+ * Used only to confirm that a GPU/oracle disagreement is a rounding tie. */
+double oracle_margin_one(const float *map, const float *frag, const oracle_params *p, int hard) {
+    if (!params_ok(p) || !frag_ok(p, frag)) return -1.0;
+    int i0, j0;
+    float fx, fy, pz;
+    address(p, frag, &i0, &j0, &fx, &fy, &pz);
+    const double X = (double)frag[0] * p->width, Y = (double)frag[1] * p->height;
+    const double zb = (double)frag[2] - (double)p->depth_bias;
+    /* depth margins over every texel the pass can read for this fragment */
+    uint8_t *saved = g_touch;
+    g_touch = NULL;
+    oracle_detail det;
+    rbsm_at(map, p, i0, j0, fx, fy, pz, hard, &det);
+    double m = 1e300;
+    const int reach = p->max_dist + 1;
+    for (int dj = -reach; dj <= reach; ++dj)
+        for (int di = -reach; di <= reach; ++di) {
+            if (abs(di) > 1 && abs(dj) > 1) continue; /* walks run along the axes */
+            const double t = fetch(map, p, i0 + di, j0 + dj);
+            const double g = fabs(zb - t);
+            if (g < m) m = g;
+        }
+    if (det.path == 2 && det.nrd[2] == 0.0f && det.nrd[3] == 0.0f) {
+        const double ffx = X - floor(X), ffy = Y - floor(Y);
+        double nx, ny;
+        {
+            const int an = abs(det.rd[0]), ap = abs(det.rd[1]);
+            const double len = an + ap - 1;
+            nx = (det.rd[1] > 0 ? ap - ffx : (an - 1) + ffx) / len;
+        }
+        {
+            const int an = abs(det.rd[3]), ap = abs(det.rd[2]);
+            const double len = an + ap - 1;
+            ny = (det.rd[2] > 0 ? ap - ffy : (an - 1) + ffy) / len;
+        }
+        const double g = fabs(ny - (1.0 - nx));
+        if (g < m) m = g;
+    }
+    g_touch = saved;
+    return m;
+}

@@ -1,0 +1,477 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check is a value printed in
+the paper (Table 1, Fig. 3), a closed form (traversal lengths on strips), a
+special case that reduces to a textbook routine (Williams' shadow test), an
+independently structured implementation on exhaustive inputs (array stencils,
+``stencil_rbsm.py``), a geometric ground truth (analytic half-planes), or an
+exact symmetry of the method.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import stencil_rbsm
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LIT, BLOCK = np.float32(0.9), np.float32(0.5)
+
+
+def params(W, H=None, bias=0.0, max_dist=16, radius=0):
+    H = W if H is None else H
+    return dict(width=W, height=H, pitch=W, depth_bias=bias, max_dist=max_dist, kernel_radius=radius)
+
+
+# --------------------------------------------------------------------------
+# Table 1 / Eq. 4: compressed discontinuity for all 2^5 centre + neighbour patterns
+# --------------------------------------------------------------------------
+
+def _table1():
+    rows = {}
+    with open(os.path.join(GOLDEN, "table1_discontinuity.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            val, dx, dy, dz = [c.strip() for c in line.split("|")]
+            rows[float(val)] = (dx, dy, dz)
+    return rows
+
+
+def test_table1_all_patterns():
+    rows = _table1()
+    dx_of = {v: m[0] for v, m in rows.items() if m[0] != "-"}
+    dy_of = {v: m[1] for v, m in rows.items() if m[1] != "-"}
+    dz_of = {v: m[2] for v, m in rows.items() if m[2] != "-"}
+    # Eq. 4 weights the top (+y) neighbour by 2: the printed d.y labels for 0.25
+    # and 0.5 are read swapped (the listing is authoritative).
+    dy_read = {v: {"top": "bottom", "bottom": "top"}.get(m, m) for v, m in dy_of.items()}
+    for centre_lit in (0, 1):
+        for nb in range(16):
+            m = np.full((5, 5), LIT, np.float32)
+            c = LIT if centre_lit else BLOCK
+            m[2, 2] = c
+            other = BLOCK if centre_lit else LIT
+            flags = [(nb >> k) & 1 for k in range(4)]  # left, right, top, bottom differ?
+            for k, (di, dj) in enumerate([(-1, 0), (1, 0), (0, 1), (0, -1)]):
+                m[2 + dj, 2 + di] = other if flags[k] else c
+            frag = [(2.5) / 5, (2.5) / 5, 0.9]
+            d = oracle.detail(m, frag, params(5), hard=False)
+            left, right, top, bottom = flags
+            want_x = {(0, 0): "none", (0, 1): "right", (1, 0): "left", (1, 1): "left-right"}[(left, right)]
+            want_y = {(0, 0): "none", (1, 0): "top", (0, 1): "bottom", (1, 1): "top-bottom"}[(top, bottom)]
+            want_z = "lit" if centre_lit else "shadowed"
+            assert dx_of[float(d.d[0])] == want_x, (centre_lit, flags, list(d.d))
+            assert dy_read[float(d.d[1])] == want_y, (centre_lit, flags, list(d.d))
+            assert dz_of[float(d.d[2])] == want_z, (centre_lit, flags, list(d.d))
+            # no discontinuity -> the plain test, no traversal (Listing 1)
+            if nb == 0:
+                assert d.path == 1 and d.vis == centre_lit
+
+
+# --------------------------------------------------------------------------
+# Fig. 3: the four shapes and the L-shape worked example
+# --------------------------------------------------------------------------
+
+def _fig3():
+    shapes = {}
+    with open(os.path.join(GOLDEN, "fig3_shapes.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, black, lit, expect = [c.strip() for c in line.split("|")]
+            pts = lambda s: [tuple(int(v) for v in p.split(",")) for p in s.split()]
+            shapes[name] = (pts(black), pts(lit), expect)
+    return shapes
+
+
+@pytest.mark.parametrize("bias", [0.0, 1e-4])
+@pytest.mark.parametrize("shape", ["I", "U", "L", "O"])
+def test_fig3_shapes(shape, bias):
+    black, lit, expect = _fig3()[shape]
+    W, off = 16, 6
+    m = np.full((W, W), LIT, np.float32)
+    for x, y in black:
+        m[off + y, off + x] = BLOCK
+    frags, xy = [], []
+    for tx, ty in lit:
+        for a in range(5):
+            for b in range(5):
+                x, y = tx + 0.1 + 0.2 * a, ty + 0.1 + 0.2 * b
+                frags.append(((off + x) / W, (off + y) / W, 0.9))
+                xy.append((x, y))
+    frags = np.array(frags, np.float32)
+    xy = np.array(xy)
+    p = params(W, bias=bias)
+    sm = oracle.shadow_map(m, frags, p)
+    assert np.all(sm == 1), "the checked texels are the lit ones of the figure"
+    hard = oracle.rbsm_hard(m, frags, p)
+    if expect == "lit":
+        assert np.all(hard == 1)
+    elif expect == "shadowed":
+        assert np.all(hard == 0)
+    else:
+        cols = [tuple(float(v) for v in c.split(",")) for c in expect.split()[1:]]
+        want = np.zeros(len(xy), bool)
+        for x0, x1, top in cols:
+            want |= (xy[:, 0] >= x0) & (xy[:, 0] < x1) & (xy[:, 1] < top)
+        assert np.array_equal(hard == 0, want)
+        # the same set is the half-plane under the line from (2,3) to (3,1)
+        below = (xy[:, 1] - 3.0) < -2.0 * (xy[:, 0] - 2.0)
+        assert np.array_equal(hard == 0, below)
+        assert int((hard == 0).sum()) == 25
+
+
+# --------------------------------------------------------------------------
+# Traversal lengths: closed form on strip patterns
+# --------------------------------------------------------------------------
+
+def _strip_case(n, stop, W=48, H=9):
+    """Fragment texel (10, 4) lit with a shadowed texel below; the n texels to
+    its right share that bottom discontinuity; then the strip stops by an
+    opposite test ("end"), by a texel without the discontinuity ("leave"), or
+    by the map border ("border")."""
+    x0, y0 = 10, 4
+    if stop == "border":
+        W = x0 + n + 1
+    m = np.full((H, W), LIT, np.float32)
+    for x in range(x0, x0 + n + 1):
+        m[y0 - 1, x] = BLOCK
+    if stop == "end":
+        m[y0, x0 + n + 1] = BLOCK
+    frag = np.array([(x0 + 0.375) / W, (y0 + 0.625) / H, 0.9], np.float32)
+    return m, frag
+
+
+def _transform(m, frag, how):
+    """Map + fragment mirrored in x ("mirror"), transposed ("transpose") or both."""
+    u, v, z = [float(t) for t in frag]
+    H, W = m.shape
+    if how in ("mirror", "transpose_mirror"):
+        m = m[:, ::-1]
+        u = 1.0 - u
+    if how in ("transpose", "transpose_mirror"):
+        m = m.T
+        u, v = v, u
+    return np.ascontiguousarray(m), np.array([u, v, z], np.float32)
+
+
+@pytest.mark.parametrize("max_dist", [1, 2, 3, 16])
+@pytest.mark.parametrize("stop", ["end", "leave", "border"])
+def test_traversal_closed_form(max_dist, stop):
+    # walk index in rd (left, right, top, bottom) after each transform of a
+    # construction that walks to the right
+    walk_index = {"none": 1, "mirror": 0, "transpose": 2, "transpose_mirror": 3}
+    for n in range(0, max_dist + 3):
+        m0, f0 = _strip_case(n, stop)
+        D = min(n + 1, max_dist + 1)
+        want = D if (stop == "end" and n + 1 <= max_dist) else -D
+        if stop == "border":  # clamp-to-edge repeats the last strip texel: the walk runs out
+            want = -(max_dist + 1)
+        for how, idx in walk_index.items():
+            m, f = (m0, f0) if how == "none" else _transform(m0, f0, how)
+            H, W = m.shape
+            d = oracle.detail(m, f, params(W, H, max_dist=max_dist), hard=True)
+            assert d.path == 2
+            assert d.rd[idx] == want, (n, stop, how, list(d.rd))
+            # the walk opposite the strip leaves the edge at once
+            opp = {0: 1, 1: 0, 2: 3, 3: 2}[idx]
+            assert d.rd[opp] == -1, (n, stop, how, list(d.rd))
+
+
+# --------------------------------------------------------------------------
+# Exhaustive 4x4 binary maps against the array-stencil implementation
+# --------------------------------------------------------------------------
+
+def _all_4x4():
+    idx = np.arange(1 << 16)
+    bits = (idx[:, None] >> np.arange(16)[None, :]) & 1  # bit b -> texel (b % 4, b // 4)
+    blocked = bits.reshape(-1, 4, 4).astype(bool)
+    return blocked
+
+
+@pytest.mark.parametrize("hard", [True, False])
+@pytest.mark.parametrize("max_dist", [1, 2, 3, 16])
+def test_exhaustive_4x4_against_stencil(max_dist, hard):
+    blocked = _all_4x4()
+    n_maps = blocked.shape[0]
+    maps = np.where(blocked, BLOCK, LIT).astype(np.float32)
+    S = (~blocked).astype(np.uint8)
+    mi = np.repeat(np.arange(n_maps, dtype=np.int32), 16)
+    t = np.tile(np.arange(16), n_maps)
+    ti, tj = t % 4, t // 4
+    kx = (mi.astype(np.int64) * 5 + t * 3 + max_dist) % 64
+    ky = (mi.astype(np.int64) * 11 + t * 7 + 3 * max_dist) % 64
+    fx = ((2 * kx + 1) / 128.0).astype(np.float32)
+    fy = ((2 * ky + 1) / 128.0).astype(np.float32)
+    frags = np.stack([(ti + fx) / 4.0, (tj + fy) / 4.0, np.full(ti.shape, 0.9)], 1).astype(np.float32)
+    p = params(4, max_dist=max_dist)
+    vis_o, rd_o, nrd_o = oracle.multi(maps, mi, frags, p, hard)
+    chunk = 1 << 14
+    for c0 in range(0, n_maps, chunk):
+        sel = slice(c0 * 16, (c0 + chunk) * 16)
+        vis_s, rd_s, nrd_s = stencil_rbsm.evaluate(S[c0:c0 + chunk], mi[sel] - c0, ti[sel], tj[sel],
+                                                   fx[sel], fy[sel], max_dist, hard)
+        assert np.array_equal(rd_o[sel], rd_s)
+        assert np.array_equal(nrd_o[sel], nrd_s)
+        assert np.array_equal(vis_o[sel], vis_s)
+    # every discontinuity pattern and every walk length up to the bound occurs
+    edge = np.any(rd_o != 0, axis=1)
+    lengths = np.unique(np.abs(rd_o[edge]))
+    assert lengths.min() == 1 and lengths.max() == min(max_dist + 1, 4 + max_dist)
+    assert set(np.unique(rd_o[edge] > 0)) == {False, True}
+
+
+# --------------------------------------------------------------------------
+# Check (a): plain shadow mapping wherever no discontinuity exists
+# --------------------------------------------------------------------------
+
+def _textbook_tests(map_, frags, p):
+    """Williams' shadow test at the fragment's texel and its 4 neighbours (clamped)."""
+    W, H = p["width"], p["height"]
+    X = frags[:, 0] * np.float32(W)
+    Y = frags[:, 1] * np.float32(H)
+    i0 = np.floor(X).astype(np.int64)
+    j0 = np.floor(Y).astype(np.int64)
+    zb = (frags[:, 2] - np.float32(p["depth_bias"])).astype(np.float32)
+
+    def lit(di, dj):
+        i = np.clip(i0 + di, 0, W - 1)
+        j = np.clip(j0 + dj, 0, H - 1)
+        return ~(zb > map_[j, i])
+
+    return lit(0, 0), [lit(-1, 0), lit(1, 0), lit(0, 1), lit(0, -1)]
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_plain_sm_where_no_discontinuity(cfg):
+    c = synth.make_config(cfg, 1000 * cfg + 1, small=True)
+    m, f, p = c["map"], c["frags"], c["params"]
+    centre, nb = _textbook_tests(m, f, p)
+    flat = np.all([n == centre for n in nb], axis=0)
+    assert flat.mean() > 0.5
+    sm = oracle.shadow_map(m, f, p)
+    assert np.array_equal(sm.astype(bool), centre)
+    hard = oracle.rbsm_hard(m, f, p)
+    soft = oracle.rsmss(m, f, p)
+    assert np.array_equal(hard[flat], sm[flat])
+    assert np.array_equal(soft[flat], sm[flat].astype(np.float32))
+    # hard recovery works on the lit side only: shadowed stays shadowed
+    assert np.all(hard[sm == 0] == 0)
+    assert np.all((soft >= 0) & (soft <= 1))
+    assert (~flat).sum() > 0
+
+
+# --------------------------------------------------------------------------
+# Check (c): analytic half-plane blockers at random angles
+# --------------------------------------------------------------------------
+
+def _halfplane(theta, off, W=64, S=8, conservative=False):
+    n = np.array([np.cos(theta), np.sin(theta)])
+    c = n @ np.array([W / 2, W / 2]) + off
+    ii, jj = np.meshgrid(np.arange(W), np.arange(W))
+    if conservative:  # a texel blocks only if the half-plane covers all of it
+        inside = np.ones(ii.shape, bool)
+        for dx in (0, 1):
+            for dy in (0, 1):
+                inside &= n[0] * (ii + dx) + n[1] * (jj + dy) < c
+    else:  # centre sampling
+        inside = n[0] * (ii + 0.5) + n[1] * (jj + 0.5) < c
+    m = np.where(inside, BLOCK, LIT).astype(np.float32)
+    g = (np.arange(W * S) + 0.5) / S
+    X, Y = np.meshgrid(g, g)
+    fr = np.stack([X.ravel() / W, Y.ravel() / W, np.full(X.size, 0.9)], 1).astype(np.float32)
+    truth = (n[0] * X + n[1] * Y < c)
+    p = params(W, bias=1e-4, max_dist=16)
+    sm = (oracle.shadow_map(m, fr, p) == 0).reshape(X.shape)
+    hard = (oracle.rbsm_hard(m, fr, p) == 0).reshape(X.shape)
+    soft = oracle.rsmss(m, fr, p).reshape(X.shape)
+    inner = (X > 8) & (X < W - 8) & (Y > 8) & (Y < W - 8)
+    return truth, sm, hard, soft, inner
+
+
+def test_halfplane_filtered_closer_than_sm():
+    rng = np.random.default_rng(1711)
+    miss_sm = miss_soft = 0
+    for _ in range(24):
+        truth, sm, hard, soft, inner = _halfplane(rng.uniform(0, 2 * np.pi), rng.uniform(-3, 3))
+        miss_sm += int((sm != truth)[inner].sum())
+        miss_soft += int(((soft < 0.5) != truth)[inner].sum())
+    assert miss_soft < 0.6 * miss_sm, (miss_soft, miss_sm)
+
+
+def test_halfplane_hard_closer_than_sm_on_conservative_maps():
+    rng = np.random.default_rng(7793)
+    miss_sm = miss_hard = 0
+    for _ in range(24):
+        truth, sm, hard, soft, inner = _halfplane(rng.uniform(0, 2 * np.pi), rng.uniform(-3, 3),
+                                                  conservative=True)
+        miss_sm += int((sm != truth)[inner].sum())
+        miss_hard += int((hard != truth)[inner].sum())
+    assert miss_hard < 0.6 * miss_sm, (miss_hard, miss_sm)
+
+
+def test_halfplane_hard_edges_less_jagged_than_sm():
+    """Std of the per-column boundary residual about the analytic edge
+    (shallow edges, centre-sampled maps).  The hard mask is biased about half a
+    texel toward shadow (the paper's shadow overestimation); the bias is
+    reported, the jaggedness is gated."""
+    rng = np.random.default_rng(31)
+    W, S = 64, 8
+    for _ in range(16):
+        theta = np.pi / 2 + rng.uniform(-0.45, 0.45) + (np.pi if rng.random() < 0.5 else 0.0)
+        truth, sm, hard, soft, inner = _halfplane(theta, rng.uniform(-3, 3), W, S)
+        cols, band = slice(12 * S, (W - 12) * S), slice(4 * S, (W - 4) * S)
+        ht = truth[band, cols].sum(0) / S
+        r_sm = sm[band, cols].sum(0) / S - ht
+        r_hard = hard[band, cols].sum(0) / S - ht
+        r_soft = (soft < 0.5)[band, cols].sum(0) / S - ht
+        assert r_hard.std() < 0.6 * r_sm.std(), (r_hard.std(), r_sm.std())
+        assert r_soft.std() < 0.6 * r_sm.std(), (r_soft.std(), r_sm.std())
+        assert 0.2 < r_hard.mean() < 0.8  # outward bias of about half a texel
+        assert abs(r_soft.mean()) < 0.2
+
+
+# --------------------------------------------------------------------------
+# Symmetries ("symmetry-aware", Sec. 4)
+# --------------------------------------------------------------------------
+
+def _random_scene(seed, W=64, n_rect=14):
+    rng = np.random.default_rng(seed)
+    m = np.full((W, W), LIT, np.float32)
+    for _ in range(n_rect):
+        x0, y0 = rng.integers(0, W, 2)
+        w, h = rng.integers(1, 18, 2)
+        m[y0:y0 + h, x0:x0 + w] = np.float32(rng.choice([0.3, 0.5, 0.7]))
+    n = 20000
+    i = rng.integers(0, W, n)
+    j = rng.integers(0, W, n)
+    fx = (2 * rng.integers(0, 64, n) + 1) / 128.0
+    fy = (2 * rng.integers(0, 64, n) + 1) / 128.0
+    z = rng.choice(np.array([0.4, 0.6, 0.9], np.float32), n)
+    fr = np.stack([(i + fx) / W, (j + fy) / W, z], 1).astype(np.float32)
+    return m, fr
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_mirror_symmetry_exact(seed):
+    m, fr = _random_scene(seed)
+    p = params(64, bias=1e-4, max_dist=16)
+    h0, s0 = oracle.rbsm_hard(m, fr, p), oracle.rsmss(m, fr, p)
+    mx = np.ascontiguousarray(m[:, ::-1])
+    fx = fr.copy(); fx[:, 0] = np.float32(1.0) - fr[:, 0]
+    my = np.ascontiguousarray(m[::-1, :])
+    fy = fr.copy(); fy[:, 1] = np.float32(1.0) - fr[:, 1]
+    for mm, ff in ((mx, fx), (my, fy)):
+        assert np.array_equal(oracle.rbsm_hard(mm, ff, p), h0)
+        assert np.array_equal(oracle.rsmss(mm, ff, p), s0)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_transpose_symmetry(seed):
+    m, fr = _random_scene(seed)
+    p = params(64, bias=1e-4, max_dist=16)
+    h0, s0 = oracle.rbsm_hard(m, fr, p), oracle.rsmss(m, fr, p)
+    mt = np.ascontiguousarray(m.T)
+    ft = fr[:, [1, 0, 2]].copy()
+    h1, s1 = oracle.rbsm_hard(mt, ft, p), oracle.rsmss(mt, ft, p)
+    diff = np.nonzero(h0 != h1)[0]
+    for k in diff:  # only where the L line ties within rounding
+        assert oracle.margin(m, fr[k], p, True) < 1e-6
+    assert np.max(np.abs(s0 - s1)) <= 2.0 ** -22
+
+
+# --------------------------------------------------------------------------
+# RSMSS properties (Listing 5)
+# --------------------------------------------------------------------------
+
+def test_rsmss_shapes_and_consistency_with_hard():
+    m, fr = _random_scene(9)
+    p = params(64, bias=1e-4, max_dist=16)
+    s = oracle.rsmss(m, fr, p)
+    h = oracle.rbsm_hard(m, fr, p)
+    assert np.all((s >= 0) & (s <= 1))
+    n_checked = 0
+    for k in range(0, fr.shape[0], 7):
+        ds = oracle.detail(m, fr[k], p, hard=False)
+        if ds.path != 2:
+            continue
+        d, nrd = list(ds.d), list(ds.nrd)
+        cx, cy = nrd[2], nrd[3]
+        if d[0] == 0.75 and d[1] == 0.75:      # short O flips the test
+            assert ds.vis == d[2]
+        elif cx == 1 and cy == 1:              # long O flips the test
+            assert ds.vis == d[2]
+        elif cx == 1:                          # U: linear in the other axis
+            sg = 1 - 2 * d[2]
+            assert ds.vis == np.float32(d[2] + sg * nrd[1])
+        if d[2] == 0 and cx == 0 and cy == 0:  # lit L: hard == (RSMSS == 1)
+            n_checked += 1
+            if (s[k] == 1) != (h[k] == 1):
+                assert oracle.margin(m, fr[k], p, True) < 1e-6
+    assert n_checked > 20
+
+
+# --------------------------------------------------------------------------
+# RPCF: box average of RSMSS over texel offsets
+# --------------------------------------------------------------------------
+
+def test_rpcf_radius_zero_is_rsmss_and_constant_field_identity():
+    m, fr = _random_scene(12)
+    p0 = params(64, bias=1e-4, max_dist=16)
+    s0 = oracle.rsmss(m, fr, p0)
+    assert np.array_equal(oracle.rsmss(m, fr, dict(p0, kernel_radius=0)), s0)
+    flat = np.full((64, 64), LIT, np.float32)
+    for r in (1, 3):
+        out = oracle.rsmss(flat, fr[:500], dict(p0, kernel_radius=r))
+        assert np.all(out == 1.0)
+
+
+def test_rpcf_matches_shifted_fragments_brute_force():
+    m, fr = _random_scene(13, W=32, n_rect=6)
+    fr = fr[:300].copy()
+    fr[:, 0] = (np.floor(fr[:, 0] * 64) + 0.5) / 64  # keep in range after the W change
+    fr[:, 1] = (np.floor(fr[:, 1] * 64) + 0.5) / 64
+    m = np.ascontiguousarray(m[:32, :32])
+    r = 2
+    p = params(32, bias=1e-4, max_dist=16, radius=r)
+    got = oracle.rsmss(m, fr, p)
+    p0 = dict(p, kernel_radius=0)
+    acc = np.zeros(fr.shape[0], np.float32)
+    for a in range(-r, r + 1):
+        for b in range(-r, r + 1):
+            sh = fr.copy()
+            sh[:, 0] = fr[:, 0] + np.float32(a / 32)
+            sh[:, 1] = fr[:, 1] + np.float32(b / 32)
+            acc = (acc + oracle.rsmss(m, sh, p0)).astype(np.float32)
+    want = (acc * np.float32(1.0 / 25.0)).astype(np.float32)
+    assert np.array_equal(got, want)
+
+
+# --------------------------------------------------------------------------
+# Input validation and read instrumentation
+# --------------------------------------------------------------------------
+
+def test_oracle_rejects_bad_input():
+    m = np.full((4, 4), LIT, np.float32)
+    f = np.array([[0.5, 0.5, 0.9]], np.float32)
+    with pytest.raises(ValueError):
+        oracle.rbsm_hard(m, f, params(4, radius=1))
+    with pytest.raises(ValueError):
+        oracle.rbsm_hard(m, f, dict(params(4), pitch=2))
+    with pytest.raises(ValueError):
+        oracle.rsmss(m, np.array([[np.nan, 0.5, 0.9]], np.float32), params(4))
+
+
+def test_read_counts():
+    m = np.full((8, 8), LIT, np.float32)
+    m[0, 0] = BLOCK
+    p = params(8)
+    # flat lit fragment: centre + 4 neighbours
+    touch, reads = oracle.touched_texels(m, np.array([[0.55, 0.55, 0.9]], np.float32), p, hard=True)
+    assert reads == 5 and touch.sum() == 5
+    # shadowed fragment in hard mode: only the centre
+    touch, reads = oracle.touched_texels(m, np.array([[0.05, 0.05, 0.9]], np.float32), p, hard=True)
+    assert reads == 1 and touch.sum() == 1
