@@ -1,0 +1,126 @@
+/*
+ * rbsm.h -- C ABI of the MI355X (gfx950) revectorization-based shadow mapping
+ * pass: hard silhouette recovery (SMSR) and revectorization-based filtering
+ * (RSMSS) from Macedo, Apolinario, Aguero, "Optimized Visibility Functions for
+ * Revectorization-Based Shadow Mapping" (arXiv 1711.07793).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is DEVICE memory owned by the caller.  The
+ * library keeps no pointer after the enqueued work completes and allocates no
+ * device memory per call.  Outputs must not overlap any input; overlapping
+ * ranges are rejected.
+ *
+ * Streams.  Work is enqueued on `stream` (0 = the default stream) and runs
+ * asynchronously; completion is observed with stream or event synchronisation.
+ * Argument checks happen on the host before anything is enqueued.
+ *
+ * Shadow map.  float32, row-major, texel (i, j) at shadow_map[j*pitch + i],
+ * 0 <= i < width, 0 <= j < height; row j holds v-texel j and +j is "top"
+ * (the +y neighbour of the discontinuity listing, Sec. 3.1.2).
+ *
+ * Fragments.  n camera fragments already in light space (the varying p of
+ * Listing 1, Sec. 3), packed as float32 (u, v, z) triples: u, v texture
+ * coordinates, z the fragment's light-space depth.  Inputs must be finite.
+ * Addressing is nearest-texel: X = u*width (binary32), texel floor(X),
+ * sub-texel fraction X - floor(X); every texel read is clamped to the map
+ * (clamp-to-edge), so u, v outside [0, 1) are legal.
+ *
+ * Shadow test (Eq. 1).  A texel of depth T is lit for a fragment of depth z
+ * unless (z - depth_bias) > T, z - depth_bias rounded to binary32 once.
+ *
+ * Errors.  Entry points return RBSM_OK (0) or a negative code; nothing is
+ * enqueued on error.  rbsm_last_error() returns a thread-local message for
+ * the calling thread's last failure.  No C++ exception crosses this ABI.
+ * Entry points are reentrant and thread-safe.
+ */
+#ifndef RBSM_H
+#define RBSM_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RBSM_OK = 0,
+    RBSM_ERR_INVALID_ARG = -1, /* bad pointer, size, parameter or overlap */
+    RBSM_ERR_HIP = -2          /* the HIP runtime reported an error */
+};
+
+/* Parameters of one pass (read at call time). */
+typedef struct {
+    int32_t width, height;  /* shadow map size in texels, 1..65536 each */
+    int64_t pitch;          /* floats between consecutive map rows, >= width */
+    float depth_bias;       /* subtracted from z before the test; 0 = Eq. 1 exactly */
+    int32_t max_dist;       /* MAXDIST of the traversal listing (Sec. 3.1.3), 1..64 */
+    int32_t kernel_radius;  /* RSMSS only: 0 = Listing 5 exactly, r > 0 = RPCF box
+                               average over (2r+1)^2 texel offsets, 0..32 */
+} rbsm_params;
+
+/*
+ * Hard RBSM: shadow silhouette recovery (Sec. 3.1; Listings 1-4).
+ * Shadowed fragments stay shadowed; a lit fragment on a shadow edge is
+ * classified by the bounded edge traversal and the normalized discontinuity
+ * space, then put in shadow by the shape rules of Listing 4 (U/O shadowed,
+ * I lit, L clipped by the revectorization line nrd.y < 1 - nrd.x).
+ *   shadow_map  [height*pitch] float32, read only
+ *   frags       [3*n] float32 (u, v, z), read only
+ *   n           number of fragments, >= 0 (0 is a no-op)
+ *   p           parameters; p->kernel_radius must be 0
+ *   out_mask    [n] uint8 written: 0 = shadow, 1 = lit, in fragment order
+ */
+int rbsm_visibility(const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
+                    uint8_t *out_mask, hipStream_t stream);
+
+/*
+ * RSMSS: revectorization-based shadow filtering (Sec. 3.2; Listings 1-3, 5).
+ * Every fragment is classified (lit and shadowed sides); the result is the
+ * fixed-size fake penumbra in [0, 1].  With p->kernel_radius = r > 0 the
+ * result is the RPCF box average: the RSMSS value evaluated at each of the
+ * (2r+1)^2 texels (i0+a, j0+b), |a|, |b| <= r, with the fragment's own
+ * sub-texel position and depth, summed in a-major order in binary32 and
+ * multiplied by 1/(2r+1)^2 (PCF over the filtered edge, Sec. 5.3).
+ *   out_vis     [n] float32 written: visibility in [0, 1], fragment order
+ * Other arguments as rbsm_visibility.
+ */
+int rsmss_visibility(const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
+                     float *out_vis, hipStream_t stream);
+
+/*
+ * Plain shadow mapping (Eq. 1 at the fragment's texel; Williams 1978), the
+ * baseline the paper compares RBSM against (Tables 2-5).
+ *   out_mask    [n] uint8 written: 0 = shadow, 1 = lit
+ * p->max_dist and p->kernel_radius are ignored.
+ */
+int sm_visibility(const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
+                  uint8_t *out_mask, hipStream_t stream);
+
+/*
+ * Read-set instrumentation (no visibility output): marks with 1 every texel
+ * the pass reads for these fragments, as the paper's listings read them --
+ * the fragment's texel; unless hard mode stops at a shadowed texel, its four
+ * neighbours; for each traversal step, the visited texel and, when it has the
+ * fragment's test result, that texel's four neighbours.  Used to count the
+ * distinct texels a pass touches (its algorithmic map bytes).
+ *   mode        0 = hard (rbsm_visibility), 1 = RSMSS (rsmss_visibility)
+ *   touched     [height*width] uint8, row-major without pitch; the caller
+ *               clears it; entries are only ever set to 1
+ */
+int rbsm_footprint(const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
+                   int32_t mode, uint8_t *touched, hipStream_t stream);
+
+/* Message for the calling thread's last non-zero return ("" if none). */
+const char *rbsm_last_error(void);
+
+/* ABI version: 100 * major + minor. */
+int32_t rbsm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBSM_H */

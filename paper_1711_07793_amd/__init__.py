@@ -1,0 +1,173 @@
+"""MI355X-native revectorization-based shadow mapping (arXiv 1711.07793).
+
+Thin Python binding of the C ABI in ``include/rbsm.h``: argument marshalling
+only.  Every step of the pass runs in the HIP kernels of ``librbsm.so``;
+PyTorch supplies device memory and the current stream.  There is no CPU
+fallback: if the library is missing the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librbsm.so")
+
+RBSM_OK = 0
+RBSM_ERR_INVALID_ARG = -1
+RBSM_ERR_HIP = -2
+
+
+class RbsmParams(ctypes.Structure):
+    """Mirror of ``rbsm_params`` (include/rbsm.h)."""
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pitch", ctypes.c_int64),
+                ("depth_bias", ctypes.c_float), ("max_dist", ctypes.c_int32),
+                ("kernel_radius", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    width: int
+    height: int
+    pitch: int | None = None
+    depth_bias: float = 0.0
+    max_dist: int = 16
+    kernel_radius: int = 0
+
+    def to_c(self) -> RbsmParams:
+        return RbsmParams(int(self.width), int(self.height),
+                          int(self.width if self.pitch is None else self.pitch),
+                          float(self.depth_bias), int(self.max_dist), int(self.kernel_radius))
+
+
+class RbsmError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load librbsm.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RbsmError(f"HIP library {LIB_PATH} is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    P = ctypes.POINTER(RbsmParams)
+    for name in ("rbsm_visibility", "rsmss_visibility", "sm_visibility"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp, vp, i64, P, vp, vp]
+        fn.restype = ctypes.c_int
+    lib.rbsm_footprint.argtypes = [vp, vp, i64, P, ctypes.c_int32, vp, vp]
+    lib.rbsm_footprint.restype = ctypes.c_int
+    lib.rbsm_last_error.argtypes = []
+    lib.rbsm_last_error.restype = ctypes.c_char_p
+    lib.rbsm_abi_version.argtypes = []
+    lib.rbsm_abi_version.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def rbsm_last_error() -> str:
+    return load_library().rbsm_last_error().decode()
+
+
+def rbsm_abi_version() -> int:
+    return int(load_library().rbsm_abi_version())
+
+
+def _params(params, shadow_map: torch.Tensor) -> RbsmParams:
+    if isinstance(params, RbsmParams):
+        return params
+    if isinstance(params, dict):
+        params = Params(**{k: v for k, v in params.items() if k in Params.__dataclass_fields__})
+    p = params.to_c()
+    if params.pitch is None and shadow_map.dim() == 2:
+        p.pitch = shadow_map.stride(0)
+    return p
+
+
+def _check_inputs(shadow_map: torch.Tensor, frags: torch.Tensor):
+    for name, t in (("shadow_map", shadow_map), ("frags", frags)):
+        if t.device.type != "cuda":
+            raise RbsmError(f"{name} must be a device tensor")
+        if t.dtype != torch.float32:
+            raise RbsmError(f"{name} must be float32")
+    if shadow_map.dim() == 2 and shadow_map.stride(1) != 1:
+        raise RbsmError("shadow_map rows must be contiguous")
+    if not frags.is_contiguous() or frags.numel() % 3 != 0:
+        raise RbsmError("frags must be contiguous (u, v, z) triples")
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _call(name: str, *args):
+    st = getattr(load_library(), name)(*args)
+    if st != RBSM_OK:
+        raise RbsmError(f"{name} returned {st}: {rbsm_last_error()}")
+
+
+def rbsm_visibility(shadow_map: torch.Tensor, frags: torch.Tensor, params, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """Hard RBSM mask (uint8 [N], 1 = lit) of ``frags`` [N, 3] against ``shadow_map`` [H, pitch]."""
+    _check_inputs(shadow_map, frags)
+    n = frags.numel() // 3
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=frags.device)
+    p = _params(params, shadow_map)
+    _call("rbsm_visibility", shadow_map.data_ptr(), frags.data_ptr(), n, ctypes.byref(p), out.data_ptr(),
+          _stream(stream))
+    return out
+
+
+def rsmss_visibility(shadow_map: torch.Tensor, frags: torch.Tensor, params, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """RSMSS visibility (float32 [N] in [0, 1]); RPCF when params.kernel_radius > 0."""
+    _check_inputs(shadow_map, frags)
+    n = frags.numel() // 3
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=frags.device)
+    p = _params(params, shadow_map)
+    _call("rsmss_visibility", shadow_map.data_ptr(), frags.data_ptr(), n, ctypes.byref(p), out.data_ptr(),
+          _stream(stream))
+    return out
+
+
+def sm_visibility(shadow_map: torch.Tensor, frags: torch.Tensor, params, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """Plain shadow mapping (Eq. 1): uint8 [N], 1 = lit."""
+    _check_inputs(shadow_map, frags)
+    n = frags.numel() // 3
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device=frags.device)
+    p = _params(params, shadow_map)
+    _call("sm_visibility", shadow_map.data_ptr(), frags.data_ptr(), n, ctypes.byref(p), out.data_ptr(),
+          _stream(stream))
+    return out
+
+
+def rbsm_footprint(shadow_map: torch.Tensor, frags: torch.Tensor, params, mode: int,
+                   touched: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Mark every texel the pass reads (uint8 [H, W]); mode 0 = hard, 1 = RSMSS."""
+    _check_inputs(shadow_map, frags)
+    n = frags.numel() // 3
+    p = _params(params, shadow_map)
+    if touched is None:
+        touched = torch.zeros((p.height, p.width), dtype=torch.uint8, device=frags.device)
+    _call("rbsm_footprint", shadow_map.data_ptr(), frags.data_ptr(), n, ctypes.byref(p), int(mode),
+          touched.data_ptr(), _stream(stream))
+    return touched
+
+
+__all__ = ["Params", "RbsmParams", "RbsmError", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+           "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

@@ -1,0 +1,88 @@
+"""Host-only checks of the C ABI library: it loads, exports every symbol the
+header declares, and rejects invalid arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbsm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                                 text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1711_07793_amd as rb
+    if not os.path.exists(rb.LIB_PATH):
+        from paper_1711_07793_amd import build
+        build.build()
+    return rb.load_library()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for want in ("rbsm_visibility", "rsmss_visibility", "sm_visibility", "rbsm_footprint",
+                 "rbsm_last_error", "rbsm_abi_version"):
+        assert want in names, names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version(lib):
+    assert lib.rbsm_abi_version() == 100
+
+
+def _p(**kw):
+    import paper_1711_07793_amd as rb
+    base = dict(width=64, height=64, pitch=64, depth_bias=0.0, max_dist=16, kernel_radius=0)
+    base.update(kw)
+    return rb.RbsmParams(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(width=0), dict(height=0), dict(width=70000), dict(pitch=10), dict(max_dist=0),
+    dict(max_dist=65), dict(kernel_radius=-1), dict(kernel_radius=33)])
+def test_invalid_params_rejected_on_host(lib, bad):
+    p = _p(**bad)
+    # fake, never dereferenced device addresses: validation fails first
+    st = lib.rsmss_visibility(0x1000, 0x100000, 16, ctypes.byref(p), 0x200000, None)
+    assert st == -1
+    assert lib.rbsm_last_error().decode().startswith("rsmss_visibility:")
+
+
+def test_hard_rejects_radius_and_nulls(lib):
+    p = _p(kernel_radius=1)
+    assert lib.rbsm_visibility(0x1000, 0x100000, 16, ctypes.byref(p), 0x200000, None) == -1
+    p = _p()
+    assert lib.rbsm_visibility(0, 0x100000, 16, ctypes.byref(p), 0x200000, None) == -1
+    assert lib.rbsm_visibility(0x1000, 0x100000, 16, None, 0x200000, None) == -1
+    assert lib.rbsm_visibility(0x1000, 0x100000, -1, ctypes.byref(p), 0x200000, None) == -1
+    assert "null" in lib.rbsm_last_error().decode() or "n < 0" in lib.rbsm_last_error().decode()
+
+
+def test_overlapping_output_rejected(lib):
+    p = _p()
+    frags = 0x100000
+    assert lib.rbsm_visibility(0x1000000, frags, 16, ctypes.byref(p), frags + 8, None) == -1
+    assert "overlap" in lib.rbsm_last_error().decode()
+
+
+def test_empty_call_is_a_noop(lib):
+    p = _p()
+    assert lib.rbsm_visibility(0, 0, 0, ctypes.byref(p), 0, None) == 0
+    assert lib.rsmss_visibility(0, 0, 0, ctypes.byref(p), 0, None) == 0
+
+
+def test_footprint_mode_checked(lib):
+    p = _p()
+    assert lib.rbsm_footprint(0x1000, 0x100000, 4, ctypes.byref(p), 7, 0x200000, None) == -1

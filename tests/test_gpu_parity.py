@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: hard masks bit-equal except on at most 1e-5 of the fragments, each of
+which must lie within 1e-6 of a decision boundary (binary64 margin from the
+oracle); RSMSS / RPCF values within 1e-5 absolute; read-set bitmaps bit-equal.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HARD_FRAC = 1e-5
+MARGIN = 1e-6
+SOFT_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rb():
+    import paper_1711_07793_amd as rb
+    rb.load_library()
+    assert torch.cuda.is_available()
+    return rb
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_hard(map_np, frags_np, params, got):
+    want = oracle.rbsm_hard(map_np, frags_np, params)
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) <= max(0, int(HARD_FRAC * len(want))), f"{len(bad)} of {len(want)} differ"
+    for k in bad:
+        assert oracle.margin(map_np, frags_np[k], params, True) < MARGIN, k
+
+
+def check_soft(map_np, frags_np, params, got, idx=None):
+    if idx is None:
+        want = oracle.rsmss(map_np, frags_np, params)
+    else:
+        want = oracle.rsmss(map_np, frags_np[idx], params)
+        got = got[idx]
+    err = np.abs(got.astype(np.float64) - want.astype(np.float64))
+    assert err.max(initial=0.0) <= SOFT_TOL, (err.max(), np.argmax(err))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("cfg,small", [(1, False), (2, True), (2, False), (3, True)])
+def test_hard_workloads(rb, cfg, small):
+    c = synth.make_config(cfg, 1000 * cfg + 1, small=small)
+    say(f"hard cfg{cfg} small={small} n={len(c['frags'])}")
+    p = dict(c["params"], kernel_radius=0)
+    got = rb.rbsm_visibility(dev(c["map"]), dev(c["frags"]), p).cpu().numpy()
+    check_hard(c["map"], c["frags"], p, got)
+
+
+@pytest.mark.parametrize("cfg,small", [(1, False), (2, True), (3, True), (3, False)])
+def test_rsmss_workloads(rb, cfg, small):
+    c = synth.make_config(cfg, 1000 * cfg + 2, small=small)
+    say(f"rsmss cfg{cfg} small={small} n={len(c['frags'])}")
+    p = dict(c["params"], kernel_radius=0)
+    got = rb.rsmss_visibility(dev(c["map"]), dev(c["frags"]), p).cpu().numpy()
+    check_soft(c["map"], c["frags"], p, got)
+
+
+def test_rpcf_small_all_and_full_sampled(rb):
+    c = synth.make_config(3, 3003, small=True)
+    r = c["light_radius"]
+    say(f"rpcf small r={r}")
+    p = dict(c["params"], kernel_radius=r)
+    got = rb.rsmss_visibility(dev(c["map"]), dev(c["frags"]), p).cpu().numpy()
+    idx = np.arange(0, len(got), 7)
+    check_soft(c["map"], c["frags"], p, got, idx)
+    assert np.all((got >= 0) & (got <= 1))
+
+
+def test_rpcf_full_size_sampled(rb):
+    c = synth.make_config(3, 3001)
+    r = c["light_radius"]
+    say(f"rpcf full r={r} n={len(c['frags'])}")
+    p = dict(c["params"], kernel_radius=r)
+    got = rb.rsmss_visibility(dev(c["map"]), dev(c["frags"]), p).cpu().numpy()
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(len(got), 1500, replace=False))
+    check_soft(c["map"], c["frags"], p, got, idx)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_footprint_matches_oracle_reads(rb, mode):
+    c = synth.make_config(2, 2001, small=True)
+    p = dict(c["params"], kernel_radius=0)
+    got = rb.rbsm_footprint(dev(c["map"]), dev(c["frags"]), p, mode).cpu().numpy()
+    want, _ = oracle.touched_texels(c["map"], c["frags"], p, hard=(mode == 0))
+    assert np.array_equal(got, want)
+
+
+def test_plain_sm(rb):
+    c = synth.make_config(2, 2001, small=True)
+    got = rb.sm_visibility(dev(c["map"]), dev(c["frags"]), c["params"]).cpu().numpy()
+    assert np.array_equal(got, oracle.shadow_map(c["map"], c["frags"], c["params"]))
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def _adversarial_maps():
+    rng = np.random.default_rng(77)
+    maps = {}
+    W = 96
+    ii, jj = np.meshgrid(np.arange(W), np.arange(W))
+    maps["checker"] = np.where((ii + jj) % 2 == 0, 0.5, 0.9).astype(np.float32)
+    maps["checker2"] = np.where(((ii // 2) + (jj // 3)) % 2 == 0, 0.5, 0.9).astype(np.float32)
+    bars = np.full((W, W), 0.9, np.float32)
+    bars[:, ::5] = 0.5
+    bars[::7, :] = 0.5
+    maps["bars"] = bars
+    border = np.full((W, W), 0.9, np.float32)
+    border[0, :] = 0.5
+    border[:, -1] = 0.5
+    border[40:60, 0:3] = 0.5
+    maps["border"] = border
+    noise = np.where(rng.random((W, W)) < 0.4, 0.5, 0.9).astype(np.float32)
+    maps["noise"] = noise
+    depths = rng.choice(np.array([0.3, 0.5, 0.7, 0.9], np.float32), (W, W))
+    maps["multidepth"] = depths
+    return maps
+
+
+def _frags_for(W, H, n, seed, spill=0.0):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-spill, 1 + spill, n)
+    v = rng.uniform(-spill, 1 + spill, n)
+    z = rng.choice(np.array([0.4, 0.6, 0.8, 0.9], np.float32), n)
+    return np.stack([u, v, z], 1).astype(np.float32)
+
+
+@pytest.mark.parametrize("name", list(_adversarial_maps().keys()))
+@pytest.mark.parametrize("max_dist", [1, 3, 16, 64])
+def test_adversarial_maps(rb, name, max_dist):
+    m = _adversarial_maps()[name]
+    H, W = m.shape
+    f = _frags_for(W, H, 40000 + 37, seed=max_dist, spill=0.05)
+    p = dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=max_dist, kernel_radius=0)
+    md, fd = dev(m), dev(f)
+    check_hard(m, f, p, rb.rbsm_visibility(md, fd, p).cpu().numpy())
+    check_soft(m, f, p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
+
+
+def test_pitch_and_nonsquare_and_tiny_maps(rb):
+    rng = np.random.default_rng(3)
+    for (H, W, pitch) in [(1, 1, 1), (1, 7, 9), (5, 1, 4), (37, 53, 64), (200, 130, 131)]:
+        full = np.zeros((H, pitch), np.float32)
+        full[:, :W] = np.where(rng.random((H, W)) < 0.35, 0.5, 0.9)
+        full[:, W:] = np.nan  # padding is never read
+        m = np.ascontiguousarray(full[:, :W])
+        f = _frags_for(W, H, 5000 + H, seed=H, spill=0.1)
+        p = dict(width=W, height=H, pitch=pitch, depth_bias=1e-4, max_dist=8, kernel_radius=0)
+        pd = dict(p, pitch=W)
+        fd = dev(f)
+        got_h = rb.rbsm_visibility(dev(full), fd, p).cpu().numpy()
+        check_hard(m, f, pd, got_h)
+        got_s = rb.rsmss_visibility(dev(full), fd, p).cpu().numpy()
+        check_soft(m, f, pd, got_s)
+        got_r = rb.rsmss_visibility(dev(full), fd, dict(p, kernel_radius=2)).cpu().numpy()
+        check_soft(m, f, dict(pd, kernel_radius=2), got_r)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4099])
+def test_ragged_sizes(rb, n):
+    c = synth.make_config(1, 1005, small=True)
+    f = np.ascontiguousarray(c["frags"][:n])
+    got = rb.rbsm_visibility(dev(c["map"]), dev(f), c["params"]).cpu().numpy()
+    check_hard(c["map"], f, c["params"], got)
+    got = rb.rsmss_visibility(dev(c["map"]), dev(f), c["params"]).cpu().numpy()
+    check_soft(c["map"], f, c["params"], got)
+
+
+def test_empty_call(rb):
+    c = synth.make_config(1, 1005, small=True)
+    m = dev(c["map"])
+    f = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    assert rb.rbsm_visibility(m, f, c["params"]).numel() == 0
+    assert rb.rsmss_visibility(m, f, c["params"]).numel() == 0
+
+
+def test_side_stream_ordering(rb):
+    c = synth.make_config(2, 2002, small=True)
+    s = torch.cuda.Stream()
+    m, f = dev(c["map"]), dev(c["frags"])
+    out = torch.full((len(c["frags"]),), 7, dtype=torch.uint8, device="cuda")
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        rb.rbsm_visibility(m, f, c["params"], out=out, stream=s)
+        res = out.clone()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    check_hard(c["map"], c["frags"], c["params"], res.cpu().numpy())
+
+
+def test_invalid_args_raise(rb):
+    c = synth.make_config(1, 1005, small=True)
+    m, f = dev(c["map"]), dev(c["frags"])
+    with pytest.raises(rb.RbsmError):
+        rb.rbsm_visibility(m, f, dict(c["params"], max_dist=0))
+    with pytest.raises(rb.RbsmError):
+        rb.rbsm_visibility(m, f, dict(c["params"], kernel_radius=3))
+    with pytest.raises(rb.RbsmError):
+        rb.rbsm_visibility(m, f.cpu(), c["params"])
