@@ -59,6 +59,13 @@ typedef struct {
     int32_t max_dist;       /* MAXDIST of the traversal listing (Sec. 3.1.3), 1..64 */
     int32_t kernel_radius;  /* RSMSS only: 0 = Listing 5 exactly, r > 0 = RPCF box
                                average over (2r+1)^2 texel offsets, 0..32 */
+    int32_t view_width;     /* layout hint, never changes a result: > 0 when the
+                               fragments are a row-major image of this many
+                               columns (fragment k is pixel (k % view_width,
+                               k / view_width); the last row may be partial), so
+                               the pass can work in 2-D screen tiles whose
+                               light-space footprint is staged in LDS; 0 = no
+                               layout (flat chunks) */
 } rbsm_params;
 
 /*

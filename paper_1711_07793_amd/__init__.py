@@ -25,7 +25,7 @@ class RbsmParams(ctypes.Structure):
     """Mirror of ``rbsm_params`` (include/rbsm.h)."""
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pitch", ctypes.c_int64),
                 ("depth_bias", ctypes.c_float), ("max_dist", ctypes.c_int32),
-                ("kernel_radius", ctypes.c_int32)]
+                ("kernel_radius", ctypes.c_int32), ("view_width", ctypes.c_int32)]
 
 
 @dataclass
@@ -36,11 +36,13 @@ class Params:
     depth_bias: float = 0.0
     max_dist: int = 16
     kernel_radius: int = 0
+    view_width: int = 0
 
     def to_c(self) -> RbsmParams:
         return RbsmParams(int(self.width), int(self.height),
                           int(self.width if self.pitch is None else self.pitch),
-                          float(self.depth_bias), int(self.max_dist), int(self.kernel_radius))
+                          float(self.depth_bias), int(self.max_dist), int(self.kernel_radius),
+                          int(self.view_width))
 
 
 class RbsmError(RuntimeError):

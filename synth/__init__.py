@@ -142,7 +142,8 @@ def make_config(k: int, seed: int, small: bool = False) -> dict:
         n = 65536 if not small else 8192
         fr = uniform_fragments(seed ^ 0x5EED_F4A6, n, np.float32(0.9))
         return dict(map=m, frags=fr, mode=HARD, scene=sc,
-                    params=dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=16, kernel_radius=0),
+                    params=dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=16, kernel_radius=0,
+                                view_width=0),
                     name="quad512_uniform65536_hard")
     if k == 2:
         W = H = 2048
@@ -151,7 +152,8 @@ def make_config(k: int, seed: int, small: bool = False) -> dict:
         sw, sh = (1920, 1080) if not small else (240, 135)
         fr = sc.camera_fragments(seed ^ 0xCA3E_2A00, sw, sh)
         return dict(map=m, frags=fr, mode=HARD, scene=sc,
-                    params=dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=32, kernel_radius=0),
+                    params=dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=32, kernel_radius=0,
+                                view_width=sw),
                     name=f"tri64_map2048_view{sw}x{sh}_hard")
     if k == 3:
         W = H = 4096
@@ -161,6 +163,7 @@ def make_config(k: int, seed: int, small: bool = False) -> dict:
         fr = sc.camera_fragments(seed ^ 0xCA3E_3A00, sw, sh)
         radius = 3 + int(uniform_floats(seed ^ 0x3AD1_0005, 1)[0] * 13)
         return dict(map=m, frags=fr, mode=RSMSS, scene=sc, light_radius=radius,
-                    params=dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=16, kernel_radius=0),
+                    params=dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=16, kernel_radius=0,
+                                view_width=sw),
                     name=f"tri256fence_map4096_view{sw}x{sh}_rsmss")
     raise ValueError(f"unknown workload {k}")

@@ -44,14 +44,14 @@ def test_abi_version(lib):
 
 def _p(**kw):
     import paper_1711_07793_amd as rb
-    base = dict(width=64, height=64, pitch=64, depth_bias=0.0, max_dist=16, kernel_radius=0)
+    base = dict(width=64, height=64, pitch=64, depth_bias=0.0, max_dist=16, kernel_radius=0, view_width=0)
     base.update(kw)
     return rb.RbsmParams(**base)
 
 
 @pytest.mark.parametrize("bad", [
     dict(width=0), dict(height=0), dict(width=70000), dict(pitch=10), dict(max_dist=0),
-    dict(max_dist=65), dict(kernel_radius=-1), dict(kernel_radius=33)])
+    dict(max_dist=65), dict(kernel_radius=-1), dict(kernel_radius=33), dict(view_width=-1)])
 def test_invalid_params_rejected_on_host(lib, bad):
     p = _p(**bad)
     # fake, never dereferenced device addresses: validation fails first

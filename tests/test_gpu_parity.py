@@ -214,3 +214,54 @@ def test_invalid_args_raise(rb):
         rb.rbsm_visibility(m, f, dict(c["params"], kernel_radius=3))
     with pytest.raises(rb.RbsmError):
         rb.rbsm_visibility(m, f.cpu(), c["params"])
+
+
+def test_unaligned_pointers_take_the_scalar_path(rb):
+    c = synth.make_config(2, 2003, small=True)
+    n = len(c["frags"])
+    buf = torch.zeros(3 * n + 8, dtype=torch.float32, device="cuda")
+    fr = buf[1:1 + 3 * n]  # 4-byte aligned only
+    fr.copy_(dev(c["frags"]).view(-1))
+    m = dev(c["map"])
+    ob = torch.zeros(n + 8, dtype=torch.uint8, device="cuda")
+    got = rb.rbsm_visibility(m, fr, c["params"], out=ob[3:3 + n]).cpu().numpy()
+    check_hard(c["map"], c["frags"], c["params"], got)
+    of = torch.zeros(n + 8, dtype=torch.float32, device="cuda")
+    got = rb.rsmss_visibility(m, fr, c["params"], out=of[1:1 + n]).cpu().numpy()
+    check_soft(c["map"], c["frags"], c["params"], got)
+
+
+def test_all_edge_fragments_fill_the_queue(rb):
+    """Every fragment of every workgroup on an edge: the LDS queue runs full."""
+    W = 64
+    ii, jj = np.meshgrid(np.arange(W), np.arange(W))
+    m = np.where((ii + jj) % 2 == 0, 0.5, 0.9).astype(np.float32)
+    rng = np.random.default_rng(11)
+    n = 3 * 1024 + 17
+    f = np.stack([rng.uniform(0, 1, n), rng.uniform(0, 1, n), np.full(n, 0.9)], 1).astype(np.float32)
+    for max_dist in (1, 7, 64):
+        p = dict(width=W, height=W, pitch=W, depth_bias=1e-4, max_dist=max_dist, kernel_radius=0)
+        check_hard(m, f, p, rb.rbsm_visibility(dev(m), dev(f), p).cpu().numpy())
+        check_soft(m, f, p, rb.rsmss_visibility(dev(m), dev(f), p).cpu().numpy())
+
+
+@pytest.mark.parametrize("vw", [0, 1, 7, 240, 241, 1000])
+def test_layout_hint_never_changes_results(rb, vw):
+    """view_width only changes how fragments are tiled (2-D tiles, partial
+    rows, flat chunks), never a result."""
+    c = synth.make_config(2, 2004, small=True)
+    f = np.ascontiguousarray(c["frags"][:30001])
+    p = dict(c["params"], view_width=vw)
+    md, fd = dev(c["map"]), dev(f)
+    check_hard(c["map"], f, p, rb.rbsm_visibility(md, fd, p).cpu().numpy())
+    check_soft(c["map"], f, p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
+
+
+def test_tiles_too_large_for_lds_read_global(rb):
+    """Uniformly scattered fragments tiled 2-D: every tile's box exceeds the
+    LDS capacity and the pass reads the map from global memory."""
+    c = synth.make_config(1, 1009)
+    p = dict(c["params"], view_width=256)
+    md, fd = dev(c["map"]), dev(c["frags"])
+    check_hard(c["map"], c["frags"], p, rb.rbsm_visibility(md, fd, p).cpu().numpy())
+    check_soft(c["map"], c["frags"], p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
