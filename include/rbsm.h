@@ -120,6 +120,30 @@ int sm_visibility(const float *shadow_map, const float *frags, int64_t n, const 
 int rbsm_footprint(const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
                    int32_t mode, uint8_t *touched, hipStream_t stream);
 
+/*
+ * Launch tuning of the hard / RSMSS (radius 0) pass.  Tuning never changes a
+ * result, only which lanes read which texels from where; it is what the
+ * project's autotuner searches.
+ */
+typedef struct {
+    int32_t tile_w;   /* screen-tile width in pixels: 16, 32 or 64 (height 1024 / tile_w);
+                         ignored (flat 1024-fragment chunks) when view_width is 0 */
+    int32_t apron;    /* texels staged around the tile's texel box, 1..8 */
+    int32_t lds_cap;  /* LDS texel capacity per workgroup, 256..12288 */
+} rbsm_tuning;
+
+/* The tuning the plain entry points use. */
+rbsm_tuning rbsm_default_tuning(void);
+
+/*
+ * rbsm_visibility (mode 0, out = uint8_t[n]) or rsmss_visibility with
+ * kernel_radius 0 (mode 1, out = float[n]) under an explicit tuning.
+ * Arguments as those entry points; tune must be valid (RBSM_ERR_INVALID_ARG
+ * otherwise).
+ */
+int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, int64_t n,
+                    const rbsm_params *p, const rbsm_tuning *tune, void *out, hipStream_t stream);
+
 /* Message for the calling thread's last non-zero return ("" if none). */
 const char *rbsm_last_error(void);
 

@@ -45,6 +45,11 @@ class Params:
                           int(self.view_width))
 
 
+class RbsmTuning(ctypes.Structure):
+    """Mirror of ``rbsm_tuning`` (include/rbsm.h)."""
+    _fields_ = [("tile_w", ctypes.c_int32), ("apron", ctypes.c_int32), ("lds_cap", ctypes.c_int32)]
+
+
 class RbsmError(RuntimeError):
     pass
 
@@ -68,6 +73,10 @@ def load_library() -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     lib.rbsm_footprint.argtypes = [vp, vp, i64, P, ctypes.c_int32, vp, vp]
     lib.rbsm_footprint.restype = ctypes.c_int
+    lib.rbsm_default_tuning.argtypes = []
+    lib.rbsm_default_tuning.restype = RbsmTuning
+    lib.rbsm_pass_tuned.argtypes = [ctypes.c_int32, vp, vp, i64, P, ctypes.POINTER(RbsmTuning), vp, vp]
+    lib.rbsm_pass_tuned.restype = ctypes.c_int
     lib.rbsm_last_error.argtypes = []
     lib.rbsm_last_error.restype = ctypes.c_char_p
     lib.rbsm_abi_version.argtypes = []
@@ -158,6 +167,25 @@ def sm_visibility(shadow_map: torch.Tensor, frags: torch.Tensor, params, out: to
     return out
 
 
+def rbsm_default_tuning() -> RbsmTuning:
+    return load_library().rbsm_default_tuning()
+
+
+def rbsm_pass_tuned(mode: int, shadow_map: torch.Tensor, frags: torch.Tensor, params, tuning,
+                    out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Hard (mode 0) or RSMSS radius-0 (mode 1) pass under an explicit tuning
+    (tile_w, apron, lds_cap); results equal the untuned entry points."""
+    _check_inputs(shadow_map, frags)
+    n = frags.numel() // 3
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8 if mode == 0 else torch.float32, device=frags.device)
+    p = _params(params, shadow_map)
+    t = tuning if isinstance(tuning, RbsmTuning) else RbsmTuning(*tuning)
+    _call("rbsm_pass_tuned", int(mode), shadow_map.data_ptr(), frags.data_ptr(), n, ctypes.byref(p),
+          ctypes.byref(t), out.data_ptr(), _stream(stream))
+    return out
+
+
 def rbsm_footprint(shadow_map: torch.Tensor, frags: torch.Tensor, params, mode: int,
                    touched: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Mark every texel the pass reads (uint8 [H, W]); mode 0 = hard, 1 = RSMSS."""
@@ -171,5 +199,5 @@ def rbsm_footprint(shadow_map: torch.Tensor, frags: torch.Tensor, params, mode: 
     return touched
 
 
-__all__ = ["Params", "RbsmParams", "RbsmError", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+__all__ = ["Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
            "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

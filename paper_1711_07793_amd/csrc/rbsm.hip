@@ -326,67 +326,76 @@ __global__ __launch_bounds__(kT) void tile_kernel(MapView m, const float *__rest
     const int vy0 = max(core_j0 - reach, 0), vy1 = min(core_j1 + reach, m.H - 1);
     const int hw = hx1 - hx0 + 1, hh = hy1 - hy0 + 1;
     const int vwid = vx1 - vx0 + 1, vh = vy1 - vy0 + 1;
-    const bool bands = (int64_t)hw * hh + (int64_t)vwid * vh <= (int64_t)cap;
-    float *s_h = s_tex, *s_v = s_tex + hw * hh;
-    if (bands) {
-        stage_rect(m, s_h, hx0, hy0, hw, hh, t);
-        stage_rect(m, s_v, vx0, vy0, vwid, vh, t);
-    }
-    __syncthreads();
+    // both bands at once when they fit together, else one after the other
+    const bool both = (int64_t)hw * hh + (int64_t)vwid * vh <= (int64_t)cap;
+    const bool h_fits = (int64_t)hw * hh <= (int64_t)cap, v_fits = (int64_t)vwid * vh <= (int64_t)cap;
+    for (int pass = 0; pass < (both ? 1 : 2); ++pass) {
+        // pass covers directions [d_lo, d_hi): 0 left, 1 right, 2 top, 3 bottom
+        const int d_lo = both ? 0 : 2 * pass, d_hi = both ? 4 : 2 * pass + 2;
+        const bool h_on = both || (pass == 0 && h_fits);
+        const bool v_on = both || (pass == 1 && v_fits);
+        float *s_h = s_tex, *s_v = both ? s_tex + hw * hh : s_tex;
+        if (pass == 1) __syncthreads();  // pass 0 walks are done with s_tex
+        if (h_on && d_lo == 0) stage_rect(m, s_h, hx0, hy0, hw, hh, t);
+        if (v_on && d_hi == 4) stage_rect(m, s_v, vx0, vy0, vwid, vh, t);
+        __syncthreads();
 
-    // 5. walks, one lane per (fragment, direction), blocks of kLdsSteps steps
-    //    with all reads of a block issued together (global memory when the
-    //    bands did not fit)
-    for (int task = t; task < 4 * ne; task += kT) {
-        const int e = task >> 2, dir = task & 3;
-        int i0, j0;
-        float zb, fx, fy;
-        state_of(e, i0, j0, zb, fx, fy);
-        const unsigned sm = q_sm[e];
-        const bool s = (sm & 16u) != 0;
-        const int dx = dir == 0 ? -1 : (dir == 1 ? 1 : 0);
-        const int dy = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
-        const bool horiz = dx != 0;
-        const bool chk_a = horiz ? (sm & BIT_T) != 0 : (sm & BIT_L) != 0;
-        const bool chk_b = horiz ? (sm & BIT_B) != 0 : (sm & BIT_R) != 0;
-        // band of this walk: rows (or columns) of the fragment +-1
-        const float *band = horiz ? s_h : s_v;
-        const int bx0 = horiz ? hx0 : vx0, by0 = horiz ? hy0 : vy0, bstride = horiz ? hw : vwid;
-        const int pa_x = horiz ? 0 : -1, pa_y = horiz ? 1 : 0;
-        const int pb_x = horiz ? 0 : 1, pb_y = horiz ? -1 : 0;
-        int rd = -(maxd + 1);
-        for (int k = 1; k <= maxd; k += kLdsSteps) {
-            float tc[kLdsSteps], ta[kLdsSteps], tb[kLdsSteps];
+        // 5. walks, one lane per (fragment, direction), blocks of kLdsSteps
+        //    steps with all reads of a block issued together (global memory
+        //    when the band did not fit)
+        const int nd = d_hi - d_lo;
+        for (int task = t; task < nd * ne; task += kT) {
+            const int e = task / nd, dir = d_lo + task % nd;
+            int i0, j0;
+            float zb, fx, fy;
+            state_of(e, i0, j0, zb, fx, fy);
+            const unsigned sm = q_sm[e];
+            const bool s = (sm & 16u) != 0;
+            const int dx = dir == 0 ? -1 : (dir == 1 ? 1 : 0);
+            const int dy = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
+            const bool horiz = dx != 0;
+            const bool chk_a = horiz ? (sm & BIT_T) != 0 : (sm & BIT_L) != 0;
+            const bool chk_b = horiz ? (sm & BIT_B) != 0 : (sm & BIT_R) != 0;
+            // band of this walk: rows (or columns) of the fragment +-1
+            const bool in_lds = horiz ? h_on : v_on;
+            const float *band = horiz ? s_h : s_v;
+            const int bx0 = horiz ? hx0 : vx0, by0 = horiz ? hy0 : vy0, bstride = horiz ? hw : vwid;
+            const int pa_x = horiz ? 0 : -1, pa_y = horiz ? 1 : 0;
+            const int pb_x = horiz ? 0 : 1, pb_y = horiz ? -1 : 0;
+            int rd = -(maxd + 1);
+            for (int k = 1; k <= maxd; k += kLdsSteps) {
+                float tc[kLdsSteps], ta[kLdsSteps], tb[kLdsSteps];
 #pragma unroll
-            for (int u = 0; u < kLdsSteps; ++u) {
-                const int ku = min(k + u, maxd);
-                const int i = i0 + ku * dx, j = j0 + ku * dy;
-                if (bands) {
-                    tc[u] = band[(clampi(j, m.H) - by0) * bstride + clampi(i, m.W) - bx0];
-                    ta[u] = band[(clampi(j + pa_y, m.H) - by0) * bstride + clampi(i + pa_x, m.W) - bx0];
-                    tb[u] = band[(clampi(j + pb_y, m.H) - by0) * bstride + clampi(i + pb_x, m.W) - bx0];
-                } else {
-                    tc[u] = texel(m, i, j);
-                    ta[u] = texel(m, i + pa_x, j + pa_y);
-                    tb[u] = texel(m, i + pb_x, j + pb_y);
+                for (int u = 0; u < kLdsSteps; ++u) {
+                    const int ku = min(k + u, maxd);
+                    const int i = i0 + ku * dx, j = j0 + ku * dy;
+                    if (in_lds) {
+                        tc[u] = band[(clampi(j, m.H) - by0) * bstride + clampi(i, m.W) - bx0];
+                        ta[u] = band[(clampi(j + pa_y, m.H) - by0) * bstride + clampi(i + pa_x, m.W) - bx0];
+                        tb[u] = band[(clampi(j + pb_y, m.H) - by0) * bstride + clampi(i + pb_x, m.W) - bx0];
+                    } else {
+                        tc[u] = texel(m, i, j);
+                        ta[u] = texel(m, i + pa_x, j + pa_y);
+                        tb[u] = texel(m, i + pb_x, j + pb_y);
+                    }
+                }
+                int stop = 0;
+#pragma unroll
+                for (int u = kLdsSteps - 1; u >= 0; --u) {
+                    const int kk = k + u;
+                    if (kk > maxd) continue;
+                    const bool end = lit(zb, tc[u]) != s;
+                    const bool share = (chk_a && lit(zb, ta[u]) != s) || (chk_b && lit(zb, tb[u]) != s);
+                    if (end) stop = kk;
+                    else if (!share) stop = -kk;
+                }
+                if (stop != 0) {
+                    rd = stop;
+                    break;
                 }
             }
-            int stop = 0;
-#pragma unroll
-            for (int u = kLdsSteps - 1; u >= 0; --u) {
-                const int kk = k + u;
-                if (kk > maxd) continue;
-                const bool end = lit(zb, tc[u]) != s;
-                const bool share = (chk_a && lit(zb, ta[u]) != s) || (chk_b && lit(zb, tb[u]) != s);
-                if (end) stop = kk;
-                else if (!share) stop = -kk;
-            }
-            if (stop != 0) {
-                rd = stop;
-                break;
-            }
+            q_rd[e][dir] = (int8_t)rd;
         }
-        q_rd[e][dir] = (int8_t)rd;
     }
     __syncthreads();
 
@@ -411,7 +420,12 @@ struct TileConfig {
     int cap;      // LDS texel capacity per workgroup
 };
 
-constexpr TileConfig kDefaultTile{32, 1, 4864};
+constexpr TileConfig kDefaultTile{32, 1, 2048};
+
+bool tuning_ok(const rbsm_tuning *t) {
+    return t && (t->tile_w == 16 || t->tile_w == 32 || t->tile_w == 64) && t->apron >= 1 && t->apron <= 8 &&
+           t->lds_cap >= 256 && t->lds_cap <= 12288;
+}
 
 template <bool HARD>
 void launch_pass(const MapView &mv, const float *frags, int64_t n, int64_t view_width, float bias, int maxd,
@@ -635,6 +649,30 @@ int rbsm_footprint(const float *shadow_map, const float *frags, int64_t n, const
     hipLaunchKernelGGL(footprint_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, mk, frags, n,
                        p->depth_bias, p->max_dist, mode == 1 ? p->kernel_radius : 0, mode == 0 ? 1 : 0);
     return launched("rbsm_footprint");
+}
+
+rbsm_tuning rbsm_default_tuning(void) {
+    rbsm_tuning t;
+    t.tile_w = kDefaultTile.tile_w;
+    t.apron = kDefaultTile.apron;
+    t.lds_cap = kDefaultTile.cap;
+    return t;
+}
+
+int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
+                    const rbsm_tuning *tune, void *out, hipStream_t stream) {
+    if (mode != 0 && mode != 1) return fail(RBSM_ERR_INVALID_ARG, "rbsm_pass_tuned: mode must be 0 or 1");
+    if (!tuning_ok(tune)) return fail(RBSM_ERR_INVALID_ARG, "rbsm_pass_tuned: invalid tuning");
+    MapView mv;
+    const int st = validate("rbsm_pass_tuned", shadow_map, frags, n, p, out, mode == 0 ? 1 : 4, false, &mv);
+    if (st != RBSM_OK) return st;
+    if (n == 0) return RBSM_OK;
+    const TileConfig cfg{tune->tile_w, tune->apron, tune->lds_cap};
+    if (mode == 0)
+        launch_pass<true>(mv, frags, n, p->view_width, p->depth_bias, p->max_dist, cfg, out, 4, stream);
+    else
+        launch_pass<false>(mv, frags, n, p->view_width, p->depth_bias, p->max_dist, cfg, out, 16, stream);
+    return launched("rbsm_pass_tuned");
 }
 
 const char *rbsm_last_error(void) { return g_err; }

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_entry_points():
     names = _declared_functions()
     for want in ("rbsm_visibility", "rsmss_visibility", "sm_visibility", "rbsm_footprint",
-                 "rbsm_last_error", "rbsm_abi_version"):
+                 "rbsm_last_error", "rbsm_abi_version", "rbsm_pass_tuned", "rbsm_default_tuning"):
         assert want in names, names
 
 
@@ -86,3 +86,13 @@ def test_empty_call_is_a_noop(lib):
 def test_footprint_mode_checked(lib):
     p = _p()
     assert lib.rbsm_footprint(0x1000, 0x100000, 4, ctypes.byref(p), 7, 0x200000, None) == -1
+
+
+def test_tuning_validated_on_host(lib):
+    import paper_1711_07793_amd as rb
+    d = lib.rbsm_default_tuning()
+    assert d.tile_w in (16, 32, 64) and d.apron >= 1 and d.lds_cap >= 256
+    p = _p()
+    for bad in (rb.RbsmTuning(24, 1, 4096), rb.RbsmTuning(32, 0, 4096), rb.RbsmTuning(32, 1, 100000)):
+        assert lib.rbsm_pass_tuned(0, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(bad), 0x200000, None) == -1
+    assert lib.rbsm_pass_tuned(3, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(d), 0x200000, None) == -1

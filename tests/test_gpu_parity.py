@@ -265,3 +265,18 @@ def test_tiles_too_large_for_lds_read_global(rb):
     md, fd = dev(c["map"]), dev(c["frags"])
     check_hard(c["map"], c["frags"], p, rb.rbsm_visibility(md, fd, p).cpu().numpy())
     check_soft(c["map"], c["frags"], p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
+
+
+@pytest.mark.parametrize("tw", [16, 32, 64])
+@pytest.mark.parametrize("cap", [256, 2048, 12288])
+def test_tuning_never_changes_results(rb, tw, cap):
+    c = synth.make_config(2, 2006, small=True)
+    md, fd = dev(c["map"]), dev(c["frags"])
+    p = c["params"]
+    want_h = rb.rbsm_visibility(md, fd, p).cpu().numpy()
+    want_s = rb.rsmss_visibility(md, fd, p).cpu().numpy()
+    for apron in (1, 4):
+        t = rb.RbsmTuning(tw, apron, cap)
+        assert np.array_equal(rb.rbsm_pass_tuned(0, md, fd, p, t).cpu().numpy(), want_h)
+        assert np.array_equal(rb.rbsm_pass_tuned(1, md, fd, p, t).cpu().numpy(), want_s)
+    check_hard(c["map"], c["frags"], p, want_h)
