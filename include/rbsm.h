@@ -144,6 +144,55 @@ rbsm_tuning rbsm_default_tuning(void);
 int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, int64_t n,
                     const rbsm_params *p, const rbsm_tuning *tune, void *out, hipStream_t stream);
 
+/*
+ * Batched form: many (view, light) passes of uneven sizes in one launch.
+ * Every job is a hard (mode 0) or RSMSS radius-0 (mode 1) pass over its own
+ * map, fragments and output; a plan launches one workgroup per screen tile of
+ * every job, so small jobs share the GPU with large ones and a frame costs a
+ * single launch (or a single graph replay).  Each output is bitwise the
+ * result of the corresponding plain entry point.
+ */
+typedef struct {
+    const float *shadow_map;  /* device, as rbsm_visibility */
+    const float *frags;       /* device, [3*n] */
+    int64_t n;                /* fragments, >= 0 */
+    rbsm_params params;       /* kernel_radius must be 0 */
+    int32_t mode;             /* 0: hard, out is uint8_t[n]; 1: RSMSS, out is float[n] */
+    void *out;                /* device; must not overlap any input or other output */
+} rbsm_job;
+
+typedef struct rbsm_plan rbsm_plan;  /* opaque; owns device tables */
+
+/* Build a plan for n_jobs (1..65535) jobs; tune may be NULL (defaults).
+ * Copies the job table to the device (synchronous).  On success *plan owns
+ * device memory until rbsm_plan_destroy. */
+int rbsm_plan_create(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tune, rbsm_plan **plan);
+
+/* Replace the jobs (pointers, depth, bias...) keeping each job's fragment
+ * count and view_width, so the tile layout is unchanged (synchronous copy;
+ * call when no launch of the plan is in flight). */
+int rbsm_plan_update(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs);
+
+/* Enqueue one batched pass on stream (graph replay after rbsm_plan_capture). */
+int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream);
+
+/* Time each candidate tuning (tile width x LDS capacity) over reps launches
+ * on stream with HIP events and keep the fastest; writes it to *chosen when
+ * non-NULL.  Outputs are recomputed, never changed.  Drops a captured graph. */
+int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, rbsm_tuning *chosen);
+
+int rbsm_plan_set_tuning(rbsm_plan *plan, const rbsm_tuning *tune);  /* drops a captured graph */
+int rbsm_plan_get_tuning(const rbsm_plan *plan, rbsm_tuning *tune);
+
+/* Capture the plan's launch on stream (not the default stream) into a HIP
+ * graph; later rbsm_plan_launch calls on any stream replay it. */
+int rbsm_plan_capture(rbsm_plan *plan, hipStream_t stream);
+
+/* Total fragments over the plan's jobs (-1 for a null plan). */
+int64_t rbsm_plan_fragments(const rbsm_plan *plan);
+
+void rbsm_plan_destroy(rbsm_plan *plan);
+
 /* Message for the calling thread's last non-zero return ("" if none). */
 const char *rbsm_last_error(void);
 

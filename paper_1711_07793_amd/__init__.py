@@ -50,6 +50,12 @@ class RbsmTuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("apron", ctypes.c_int32), ("lds_cap", ctypes.c_int32)]
 
 
+class RbsmJob(ctypes.Structure):
+    """Mirror of ``rbsm_job`` (include/rbsm.h)."""
+    _fields_ = [("shadow_map", ctypes.c_void_p), ("frags", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("params", RbsmParams), ("mode", ctypes.c_int32), ("out", ctypes.c_void_p)]
+
+
 class RbsmError(RuntimeError):
     pass
 
@@ -77,6 +83,25 @@ def load_library() -> ctypes.CDLL:
     lib.rbsm_default_tuning.restype = RbsmTuning
     lib.rbsm_pass_tuned.argtypes = [ctypes.c_int32, vp, vp, i64, P, ctypes.POINTER(RbsmTuning), vp, vp]
     lib.rbsm_pass_tuned.restype = ctypes.c_int
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.rbsm_plan_create.argtypes = [ctypes.POINTER(RbsmJob), ctypes.c_int32, ctypes.POINTER(RbsmTuning), PP]
+    lib.rbsm_plan_create.restype = ctypes.c_int
+    lib.rbsm_plan_update.argtypes = [vp, ctypes.POINTER(RbsmJob), ctypes.c_int32]
+    lib.rbsm_plan_update.restype = ctypes.c_int
+    lib.rbsm_plan_launch.argtypes = [vp, vp]
+    lib.rbsm_plan_launch.restype = ctypes.c_int
+    lib.rbsm_plan_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(RbsmTuning)]
+    lib.rbsm_plan_autotune.restype = ctypes.c_int
+    lib.rbsm_plan_set_tuning.argtypes = [vp, ctypes.POINTER(RbsmTuning)]
+    lib.rbsm_plan_set_tuning.restype = ctypes.c_int
+    lib.rbsm_plan_get_tuning.argtypes = [vp, ctypes.POINTER(RbsmTuning)]
+    lib.rbsm_plan_get_tuning.restype = ctypes.c_int
+    lib.rbsm_plan_capture.argtypes = [vp, vp]
+    lib.rbsm_plan_capture.restype = ctypes.c_int
+    lib.rbsm_plan_fragments.argtypes = [vp]
+    lib.rbsm_plan_fragments.restype = ctypes.c_int64
+    lib.rbsm_plan_destroy.argtypes = [vp]
+    lib.rbsm_plan_destroy.restype = None
     lib.rbsm_last_error.argtypes = []
     lib.rbsm_last_error.restype = ctypes.c_char_p
     lib.rbsm_abi_version.argtypes = []
@@ -199,5 +224,81 @@ def rbsm_footprint(shadow_map: torch.Tensor, frags: torch.Tensor, params, mode: 
     return touched
 
 
-__all__ = ["Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+class Plan:
+    """Batched form: one launch (or graph replay) for many (view, light) jobs.
+
+    ``jobs`` is a list of dicts with ``map`` (float32 device tensor [H, pitch]),
+    ``frags`` (float32 device tensor [N, 3]), ``params`` (dict or Params,
+    kernel_radius 0), ``mode`` (0 hard, 1 RSMSS) and ``out`` (uint8 [N] or
+    float32 [N] device tensor).  The tensors are kept alive by the plan.
+    """
+
+    def __init__(self, jobs, tuning=None):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        arr, keep = self._marshal(jobs)
+        t = None if tuning is None else ctypes.byref(
+            tuning if isinstance(tuning, RbsmTuning) else RbsmTuning(*tuning))
+        st = self._lib.rbsm_plan_create(arr, len(jobs), t, ctypes.byref(self._h))
+        if st != RBSM_OK:
+            raise RbsmError(f"rbsm_plan_create returned {st}: {rbsm_last_error()}")
+        self._keep = keep
+
+    @staticmethod
+    def _marshal(jobs):
+        arr = (RbsmJob * len(jobs))()
+        keep = []
+        for k, j in enumerate(jobs):
+            m, f, o = j["map"], j["frags"], j["out"]
+            _check_inputs(m, f)
+            mode = int(j.get("mode", 0))
+            want = torch.uint8 if mode == 0 else torch.float32
+            if o.dtype != want or not o.is_contiguous() or o.numel() != f.numel() // 3:
+                raise RbsmError(f"job {k}: out must be a contiguous {want} tensor of N elements")
+            arr[k] = RbsmJob(m.data_ptr(), f.data_ptr(), f.numel() // 3, _params(j["params"], m), mode,
+                             o.data_ptr())
+            keep += [m, f, o]
+        return arr, keep
+
+    def update(self, jobs):
+        arr, keep = self._marshal(jobs)
+        _call("rbsm_plan_update", self._h, arr, len(jobs))
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _call("rbsm_plan_launch", self._h, _stream(stream))
+
+    def autotune(self, reps: int = 5, stream=None) -> RbsmTuning:
+        t = RbsmTuning()
+        _call("rbsm_plan_autotune", self._h, _stream(stream), int(reps), ctypes.byref(t))
+        return t
+
+    @property
+    def tuning(self) -> RbsmTuning:
+        t = RbsmTuning()
+        _call("rbsm_plan_get_tuning", self._h, ctypes.byref(t))
+        return t
+
+    @tuning.setter
+    def tuning(self, t):
+        t = t if isinstance(t, RbsmTuning) else RbsmTuning(*t)
+        _call("rbsm_plan_set_tuning", self._h, ctypes.byref(t))
+
+    def capture(self, stream):
+        _call("rbsm_plan_capture", self._h, _stream(stream))
+
+    @property
+    def fragments(self) -> int:
+        return int(self._lib.rbsm_plan_fragments(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rbsm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+
+__all__ = ["Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
            "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

@@ -10,6 +10,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
+#include <vector>
+
+#include <algorithm>
 
 #include "rbsm.h"
 #include "rbsm_device.hpp"
@@ -117,24 +121,38 @@ __device__ __forceinline__ float fetch(const MapView &m, const Staged &st, int i
 //     function and stores.
 // Staging, tile shape and queues only decide where texels are read from and
 // by which lane: every result equals the per-fragment listing.
+// Workgroup-shared state of one tile (the staged texels live in the dynamic
+// LDS array that follows it).
+struct TileShared {
+    int box[kT / 64][4];
+    int16_t slot[kTileF];
+    uint8_t sm[kTileF];    // bit 4: centre test, bits 0-3: discontinuity mask
+    int qi[kState], qj[kState];
+    float qz[kState], qfx[kState], qfy[kState];
+    int8_t rd[kTileF][4];  // left, right, top, bottom
+    int count;
+};
+
 template <bool HARD, int TW>
-__global__ __launch_bounds__(kT) void tile_kernel(MapView m, const float *__restrict__ frags, int64_t n,
-                                                  int64_t vw, int64_t tiles_x, float bias, int maxd, int apron,
-                                                  int cap, int vec_ok, void *__restrict__ out_v) {
+__device__ __forceinline__ void process_tile(MapView m, const float *__restrict__ frags, int64_t n, int64_t vw,
+                                             int64_t tiles_x, float bias, int maxd, int apron, int cap,
+                                             int vec_ok, void *__restrict__ out_v, int64_t tile_id,
+                                             TileShared &sh, float *s_tex) {
     constexpr int TH = kTileF / TW;
     constexpr int LPR = TW / kF;
-    extern __shared__ float s_tex[];
-    __shared__ int s_box[kT / 64][4];
-    __shared__ int16_t q_slot[kTileF];
-    __shared__ uint8_t q_sm[kTileF];    // bit 4: centre test, bits 0-3: discontinuity mask
-    __shared__ int q_i[kState], q_j[kState];
-    __shared__ float q_z[kState], q_fx[kState], q_fy[kState];
-    __shared__ int8_t q_rd[kTileF][4];  // left, right, top, bottom
-    __shared__ int q_count;
+    auto &s_box = sh.box;
+    auto &q_slot = sh.slot;
+    auto &q_sm = sh.sm;
+    auto &q_i = sh.qi;
+    auto &q_j = sh.qj;
+    auto &q_z = sh.qz;
+    auto &q_fx = sh.qfx;
+    auto &q_fy = sh.qfy;
+    auto &q_rd = sh.rd;
+    int &q_count = sh.count;
 
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int64_t tile_id = xcd_block(blockIdx.x, gridDim.x);
     const int64_t tyi = tile_id / tiles_x, txi = tile_id % tiles_x;
     const int64_t px0 = txi * TW + (int64_t)(t % LPR) * kF;
     const int64_t k0 = (tyi * TH + t / LPR) * vw + px0;
@@ -413,6 +431,46 @@ __global__ __launch_bounds__(kT) void tile_kernel(MapView m, const float *__rest
     }
 }
 
+template <bool HARD, int TW>
+__global__ __launch_bounds__(kT) void tile_kernel(MapView m, const float *__restrict__ frags, int64_t n,
+                                                  int64_t vw, int64_t tiles_x, float bias, int maxd, int apron,
+                                                  int cap, int vec_ok, void *__restrict__ out_v) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    process_tile<HARD, TW>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v,
+                           xcd_block(blockIdx.x, gridDim.x), sh, s_tex);
+}
+
+// One job of a batched launch: a (view, light) pass over its own map,
+// fragments and output, owning tiles [tile_base, tile_base + tiles).
+struct JobDev {
+    MapView m;
+    const float *frags;
+    void *out;
+    int64_t n, vw, tiles_x, tile_base;
+    float bias;
+    int maxd, vec_ok, mode;  // mode 0 hard, 1 RSMSS
+};
+
+// Batched pass: one workgroup per tile of any job; block_job maps the
+// (XCD-ordered) workgroup index to its job.  Each tile runs exactly the code
+// of the single-view pass, so every output is bitwise the same.
+template <int TW>
+__global__ __launch_bounds__(kT) void batch_kernel(const JobDev *__restrict__ jobs,
+                                                   const uint16_t *__restrict__ block_job, int apron, int cap) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
+    const JobDev J = jobs[block_job[g]];
+    const int64_t tile = g - J.tile_base;
+    if (J.mode == 0)
+        process_tile<true, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
+                               tile, sh, s_tex);
+    else
+        process_tile<false, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
+                                tile, sh, s_tex);
+}
+
 // Launch configuration of the main pass (defaults of the plain entry points).
 struct TileConfig {
     int tile_w;   // 16, 32, 64 (2-D tiles) or 1024 (flat)
@@ -585,6 +643,140 @@ int launched(const char *fn) {
 
 unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Tile layout of one job in a batched launch: 2-D tiles of width tw over its
+// image (flat jobs are laid out as rows of 1024 fragments).
+struct JobLayout {
+    int64_t vw, tiles_x, tiles;
+};
+
+JobLayout job_layout(int64_t n, int64_t view_width, int tw) {
+    JobLayout L;
+    L.vw = view_width > 0 ? view_width : 1024;
+    const int th = kTileF / tw;
+    const int64_t rows = (n + L.vw - 1) / L.vw;
+    L.tiles_x = (L.vw + tw - 1) / tw;
+    L.tiles = n > 0 ? L.tiles_x * ((rows + th - 1) / th) : 0;
+    return L;
+}
+
+}  // namespace
+
+struct rbsm_plan {
+    int device = 0;
+    std::vector<rbsm_job> jobs;
+    rbsm_tuning tune{};
+    JobDev *d_jobs = nullptr;
+    uint16_t *d_block_job = nullptr;
+    int64_t blocks = 0;
+    int64_t fragments = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(rbsm_plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+void free_tables(rbsm_plan *p) {
+    if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_block_job) (void)hipFree(p->d_block_job);
+    p->d_jobs = nullptr;
+    p->d_block_job = nullptr;
+}
+
+// Validate jobs and build (and upload) the device job table and the
+// block -> job map for the plan's tile width.
+int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool keep_layout) {
+    const char *fn = keep_layout ? "rbsm_plan_update" : "rbsm_plan_create";
+    if (!jobs || n_jobs < 1 || n_jobs > 65535) return fail(RBSM_ERR_INVALID_ARG, "%s: need 1..65535 jobs", fn);
+    if (keep_layout && (size_t)n_jobs != plan->jobs.size())
+        return fail(RBSM_ERR_INVALID_ARG, "%s: job count differs from the plan", fn);
+    std::vector<JobDev> dev(n_jobs);
+    std::vector<uint16_t> block_job;
+    int64_t base = 0, frags = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const rbsm_job &J = jobs[j];
+        if (J.mode != 0 && J.mode != 1) return fail(RBSM_ERR_INVALID_ARG, "%s: job mode must be 0 or 1", fn);
+        MapView mv;
+        const int st = validate(fn, J.shadow_map, J.frags, J.n, &J.params, J.out, J.mode == 0 ? 1 : 4, false, &mv);
+        if (st != RBSM_OK) return st;
+        if (keep_layout && (J.n != plan->jobs[j].n || J.params.view_width != plan->jobs[j].params.view_width))
+            return fail(RBSM_ERR_INVALID_ARG, "%s: a job's n or view_width differs from the plan", fn);
+        const JobLayout L = job_layout(J.n, J.params.view_width, plan->tune.tile_w);
+        JobDev &D = dev[j];
+        D.m = mv;
+        D.frags = J.frags;
+        D.out = J.out;
+        D.n = J.n;
+        D.vw = L.vw;
+        D.tiles_x = L.tiles_x;
+        D.tile_base = base;
+        D.bias = J.params.depth_bias;
+        D.maxd = J.params.max_dist;
+        D.mode = J.mode;
+        D.vec_ok = ((uintptr_t)J.frags % 16 == 0) && ((uintptr_t)J.out % (J.mode == 0 ? 4 : 16) == 0) &&
+                   (L.vw % 4 == 0);
+        for (int64_t b = 0; b < L.tiles; ++b) block_job.push_back((uint16_t)j);
+        base += L.tiles;
+        frags += J.n;
+    }
+    // outputs must not overlap each other or any input of any job
+    for (int32_t a = 0; a < n_jobs; ++a) {
+        const size_t ob = (size_t)jobs[a].n * (jobs[a].mode == 0 ? 1 : 4);
+        for (int32_t b = 0; b < n_jobs; ++b) {
+            if (jobs[a].n == 0 || jobs[b].n == 0) continue;
+            const rbsm_params &P = jobs[b].params;
+            const size_t mb = ((size_t)(P.height - 1) * (size_t)P.pitch + (size_t)P.width) * 4u;
+            if (overlaps(jobs[a].out, ob, jobs[b].shadow_map, mb) ||
+                overlaps(jobs[a].out, ob, jobs[b].frags, (size_t)jobs[b].n * 12u) ||
+                (a != b && overlaps(jobs[a].out, ob, jobs[b].out, (size_t)jobs[b].n * (jobs[b].mode == 0 ? 1 : 4))))
+                return fail(RBSM_ERR_INVALID_ARG, "%s: a job output overlaps another array", fn);
+        }
+    }
+    if (base > ((int64_t)1 << 24)) return fail(RBSM_ERR_INVALID_ARG, "%s: more than 2^24 tiles", fn);
+    if (!keep_layout || base != plan->blocks) {
+        free_tables(plan);
+        if (hipMalloc(&plan->d_jobs, sizeof(JobDev) * (size_t)n_jobs) != hipSuccess ||
+            hipMalloc(&plan->d_block_job, sizeof(uint16_t) * (size_t)std::max<int64_t>(base, 1)) != hipSuccess) {
+            free_tables(plan);
+            return fail(RBSM_ERR_HIP, "%s: could not allocate the job tables", fn);
+        }
+    }
+    if (hipMemcpy(plan->d_jobs, dev.data(), sizeof(JobDev) * (size_t)n_jobs, hipMemcpyHostToDevice) != hipSuccess ||
+        (base > 0 && hipMemcpy(plan->d_block_job, block_job.data(), sizeof(uint16_t) * (size_t)base,
+                               hipMemcpyHostToDevice) != hipSuccess))
+        return fail(RBSM_ERR_HIP, "%s: could not upload the job tables", fn);
+    plan->jobs.assign(jobs, jobs + n_jobs);
+    plan->blocks = base;
+    plan->fragments = frags;
+    return RBSM_OK;
+}
+
+void launch_batch(const rbsm_plan *p, hipStream_t stream) {
+    if (p->blocks == 0) return;
+    const dim3 grid((unsigned)p->blocks), block(kT);
+    const size_t lds = (size_t)p->tune.lds_cap * sizeof(float);
+    switch (p->tune.tile_w) {
+        case 16:
+            hipLaunchKernelGGL(batch_kernel<16>, grid, block, lds, stream, p->d_jobs, p->d_block_job, p->tune.apron,
+                               p->tune.lds_cap);
+            break;
+        case 64:
+            hipLaunchKernelGGL(batch_kernel<64>, grid, block, lds, stream, p->d_jobs, p->d_block_job, p->tune.apron,
+                               p->tune.lds_cap);
+            break;
+        default:
+            hipLaunchKernelGGL(batch_kernel<32>, grid, block, lds, stream, p->d_jobs, p->d_block_job, p->tune.apron,
+                               p->tune.lds_cap);
+            break;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -673,6 +865,131 @@ int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, i
     else
         launch_pass<false>(mv, frags, n, p->view_width, p->depth_bias, p->max_dist, cfg, out, 16, stream);
     return launched("rbsm_pass_tuned");
+}
+
+int rbsm_plan_create(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tune, rbsm_plan **plan) {
+    if (!plan) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_create: plan is null");
+    *plan = nullptr;
+    if (tune && !tuning_ok(tune)) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_create: invalid tuning");
+    rbsm_plan *p = new (std::nothrow) rbsm_plan();
+    if (!p) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_create: out of host memory");
+    p->tune = tune ? *tune : rbsm_default_tuning();
+    (void)hipGetDevice(&p->device);
+    const int st = build_tables(p, jobs, n_jobs, false);
+    if (st != RBSM_OK) {
+        free_tables(p);
+        delete p;
+        return st;
+    }
+    *plan = p;
+    return RBSM_OK;
+}
+
+int rbsm_plan_update(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs) {
+    if (!plan) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_update: plan is null");
+    return build_tables(plan, jobs, n_jobs, true);
+}
+
+int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream) {
+    if (!plan) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_launch: plan is null");
+    if (plan->exec) {
+        if (hipGraphLaunch(plan->exec, stream) != hipSuccess)
+            return fail(RBSM_ERR_HIP, "rbsm_plan_launch: graph launch failed");
+        return RBSM_OK;
+    }
+    launch_batch(plan, stream);
+    return launched("rbsm_plan_launch");
+}
+
+int rbsm_plan_set_tuning(rbsm_plan *plan, const rbsm_tuning *tune) {
+    if (!plan || !tuning_ok(tune)) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_set_tuning: invalid argument");
+    drop_graph(plan);
+    if (tune->tile_w != plan->tune.tile_w) {
+        const rbsm_tuning old = plan->tune;
+        plan->tune = *tune;
+        const std::vector<rbsm_job> jobs = plan->jobs;
+        const int st = build_tables(plan, jobs.data(), (int32_t)jobs.size(), false);
+        if (st != RBSM_OK) {
+            plan->tune = old;
+            return st;
+        }
+    }
+    plan->tune = *tune;
+    return RBSM_OK;
+}
+
+int rbsm_plan_get_tuning(const rbsm_plan *plan, rbsm_tuning *tune) {
+    if (!plan || !tune) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_get_tuning: null argument");
+    *tune = plan->tune;
+    return RBSM_OK;
+}
+
+int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, rbsm_tuning *chosen) {
+    if (!plan || reps < 1) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_autotune: invalid argument");
+    drop_graph(plan);
+    const int tws[] = {16, 32, 64};
+    const int caps[] = {2048, 3072, 4096};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RBSM_ERR_HIP, "rbsm_plan_autotune: could not create events");
+    rbsm_tuning best = plan->tune;
+    float best_ms = 1e30f;
+    int status = RBSM_OK;
+    for (int tw : tws) {
+        for (int cap : caps) {
+            rbsm_tuning cand{tw, 1, cap};
+            if ((status = rbsm_plan_set_tuning(plan, &cand)) != RBSM_OK) break;
+            launch_batch(plan, stream);  // warm-up
+            (void)hipEventRecord(e0, stream);
+            for (int r = 0; r < reps; ++r) launch_batch(plan, stream);
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+                status = fail(RBSM_ERR_HIP, "rbsm_plan_autotune: a timed launch failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+        }
+        if (status != RBSM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != RBSM_OK) return status;
+    if ((status = rbsm_plan_set_tuning(plan, &best)) != RBSM_OK) return status;
+    if (chosen) *chosen = best;
+    return RBSM_OK;
+}
+
+int rbsm_plan_capture(rbsm_plan *plan, hipStream_t stream) {
+    if (!plan || !stream) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_capture: need a plan and a non-default stream");
+    drop_graph(plan);
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(RBSM_ERR_HIP, "rbsm_plan_capture: could not begin capture");
+    launch_batch(plan, stream);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(stream, &g) != hipSuccess || !g)
+        return fail(RBSM_ERR_HIP, "rbsm_plan_capture: capture failed");
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(RBSM_ERR_HIP, "rbsm_plan_capture: could not instantiate the graph");
+    }
+    plan->graph = g;
+    plan->exec = x;
+    return RBSM_OK;
+}
+
+int64_t rbsm_plan_fragments(const rbsm_plan *plan) { return plan ? plan->fragments : -1; }
+
+void rbsm_plan_destroy(rbsm_plan *plan) {
+    if (!plan) return;
+    drop_graph(plan);
+    free_tables(plan);
+    delete plan;
 }
 
 const char *rbsm_last_error(void) { return g_err; }

@@ -59,6 +59,9 @@ def _load():
     lib.synth_frags_uniform.restype = None
     lib.synth_frags_camera.argtypes = [vp, u64, ctypes.c_int, ctypes.c_int, ctypes.c_double, vp]
     lib.synth_frags_camera.restype = ctypes.c_int
+    lib.synth_frags_camera_rows.argtypes = [vp, u64, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_int, vp]
+    lib.synth_frags_camera_rows.restype = ctypes.c_int
     lib.synth_uniform_f32.argtypes = [u64, i64, vp]
     lib.synth_uniform_f32.restype = None
     _lib = lib
@@ -100,6 +103,16 @@ class Scene:
         st = _load().synth_frags_camera(self._h, seed, width, height, vfov_deg, _ptr(out))
         if st != 0:
             raise RuntimeError(f"camera footprint left the map (status {st})")
+        return out
+
+
+    def camera_rows(self, seed: int, width: int, height: int, r0: int, r1: int,
+                    vfov_deg: float = 40.0) -> np.ndarray:
+        """Rows [r0, r1) of the camera image of ``camera_fragments`` (same values)."""
+        out = np.empty(((r1 - r0) * width, 3), dtype=np.float32)
+        st = _load().synth_frags_camera_rows(self._h, seed, width, height, vfov_deg, r0, r1, _ptr(out))
+        if st != 0:
+            raise RuntimeError(f"camera rows failed (status {st})")
         return out
 
 
@@ -167,3 +180,56 @@ def make_config(k: int, seed: int, small: bool = False) -> dict:
                                 view_width=sw),
                     name=f"tri256fence_map4096_view{sw}x{sh}_rsmss")
     raise ValueError(f"unknown workload {k}")
+
+
+def make_batched(seed: int, small: bool = False) -> dict:
+    """Batched workload: 16 shadow maps (a directional light's 4 cascades of
+    8192^2, 4096^2, 2048^2, 1024^2 and 12 spot lights of 1024^2..4096^2, each a
+    random-triangle scene) and 8 views (two each of 1280x720, 1920x1080,
+    2560x1440, 3840x2160).  Each view's rows are split among the 4 cascades
+    (Dirichlet fractions, near rows to the finest cascade) and 2 spot lights
+    each cover a band of U(0.3, 1.0) of its rows: 48 jobs of uneven size.
+    Cascade jobs are hard (MAXDIST 32 on the two finest maps, 16 after),
+    spot jobs RSMSS radius 0 (MAXDIST 16); depth bias 1e-4.  ``small``
+    divides every map side by 16 and every view side by 8 (test size).
+
+    Returns dict(maps=[float32 [S, S]], jobs=[dict(map=i, frags=[N, 3],
+    params=..., mode=0/1, view=v, rows=(r0, r1))]).
+    """
+    rng = np.random.default_rng(seed)
+    div_m, div_v = (16, 8) if small else (1, 1)
+    cascade = [8192, 4096, 2048, 1024]
+    spot = [int(rng.choice([1024, 2048, 4096])) for _ in range(12)]
+    sizes = [s // div_m for s in cascade + spot]
+    scenes = [triangle_scene(seed * 100 + i, s, s, 64, fence=False) for i, s in enumerate(sizes)]
+    maps = [sc.raster() for sc in scenes]
+    views = [(1280, 720), (1280, 720), (1920, 1080), (1920, 1080), (2560, 1440), (2560, 1440),
+             (3840, 2160), (3840, 2160)]
+    jobs = []
+    for v, (ws, hs) in enumerate(views):
+        ws, hs = ws // div_v, hs // div_v
+        cam_seed = seed * 1000 + v
+        frac = rng.dirichlet([2.0, 2.0, 2.0, 2.0])
+        cuts = np.concatenate([[0], np.round(np.cumsum(frac) * hs).astype(int)])
+        cuts[-1] = hs
+        # rows run far (top) to near (bottom): the nearest rows use cascade 0
+        for c in range(4):
+            r1, r0 = hs - cuts[c], hs - cuts[c + 1]
+            if r1 <= r0:
+                continue
+            S = sizes[c]
+            fr = scenes[c].camera_rows(cam_seed, ws, hs, r0, r1)
+            jobs.append(dict(map=c, frags=fr, mode=0, view=v, rows=(r0, r1),
+                             params=dict(width=S, height=S, pitch=S, depth_bias=1e-4,
+                                         max_dist=32 if c < 2 else 16, kernel_radius=0, view_width=ws)))
+        for sl in rng.choice(12, size=2, replace=False):
+            m_idx = 4 + int(sl)
+            cover = rng.uniform(0.3, 1.0)
+            nr = max(1, int(round(cover * hs)))
+            r0 = int(rng.integers(0, hs - nr + 1))
+            S = sizes[m_idx]
+            fr = scenes[m_idx].camera_rows(cam_seed, ws, hs, r0, r0 + nr)
+            jobs.append(dict(map=m_idx, frags=fr, mode=1, view=v, rows=(r0, r0 + nr),
+                             params=dict(width=S, height=S, pitch=S, depth_bias=1e-4, max_dist=16,
+                                         kernel_radius=0, view_width=ws)))
+    return dict(maps=maps, jobs=jobs, views=[(w // div_v, h // div_v) for w, h in views])

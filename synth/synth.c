@@ -361,7 +361,21 @@ static int project(const camera *cam, int Ws, int Hs, const double P[3], double 
  * row-major screen order, (u, v, z) float32 of the first surface hit (the
  * nearest blocker, else the receiver).  Returns 0, or -1 when some pixel
  * lands outside [0,1)^2 (the placement guarantees it does not). */
-int synth_frags_camera(const synth_scene *sc, uint64_t seed, int Ws, int Hs, double vfov_deg,
+static int camera_rows(const synth_scene *sc, uint64_t seed, int Ws, int Hs, double vfov_deg, int r0, int r1,
+                       float *out);
+
+int synth_frags_camera(const synth_scene *sc, uint64_t seed, int Ws, int Hs, double vfov_deg, float *out) {
+    return camera_rows(sc, seed, Ws, Hs, vfov_deg, 0, Hs, out);
+}
+
+/* Rows [r0, r1) of the same camera image: (r1 - r0) * Ws fragments. */
+int synth_frags_camera_rows(const synth_scene *sc, uint64_t seed, int Ws, int Hs, double vfov_deg, int r0, int r1,
+                            float *out) {
+    if (r0 < 0 || r1 > Hs || r0 > r1) return -3;
+    return camera_rows(sc, seed, Ws, Hs, vfov_deg, r0, r1, out);
+}
+
+static int camera_rows(const synth_scene *sc, uint64_t seed, int Ws, int Hs, double vfov_deg, int r0, int r1,
                        float *out) {
     synth_rng r;
     synth_rng_seed(&r, seed);
@@ -383,8 +397,8 @@ int synth_frags_camera(const synth_scene *sc, uint64_t seed, int Ws, int Hs, dou
     cam.C[1] = 0.5 - s * cam.f[1];
     cam.C[2] = zc;
 
-    const int64_t npix = (int64_t)Ws * Hs;
-    int32_t *winner = (int32_t *)malloc((size_t)npix * sizeof(int32_t));
+    const int64_t npix = (int64_t)Ws * (r1 - r0);
+    int32_t *winner = (int32_t *)malloc((size_t)(npix > 0 ? npix : 1) * sizeof(int32_t));
     if (!winner) return -2;
     for (int64_t k = 0; k < npix; ++k) winner[k] = -1;
 
@@ -406,15 +420,20 @@ int synth_frags_camera(const synth_scene *sc, uint64_t seed, int Ws, int Hs, dou
                 ymin = py < ymin ? py : ymin; ymax = py > ymax ? py : ymax;
             }
             if (ok) {
+                /* clamp before converting: a vertex near the camera plane projects far away */
+                xmin = fmax(xmin, -2.0); xmax = fmin(xmax, (double)Ws + 1.0);
+                ymin = fmax(ymin, -2.0); ymax = fmin(ymax, (double)Hs + 1.0);
                 x_lo = (int)floor(xmin) - 1; x_hi = (int)ceil(xmax) + 1;
                 y_lo = (int)floor(ymin) - 1; y_hi = (int)ceil(ymax) + 1;
                 x_lo = x_lo < 0 ? 0 : x_lo; y_lo = y_lo < 0 ? 0 : y_lo;
                 x_hi = x_hi > Ws - 1 ? Ws - 1 : x_hi; y_hi = y_hi > Hs - 1 ? Hs - 1 : y_hi;
             }
         }
+        if (y_lo < r0) y_lo = r0;
+        if (y_hi > r1 - 1) y_hi = r1 - 1;
         for (int py = y_lo; py <= y_hi; ++py) {
             for (int px = x_lo; px <= x_hi; ++px) {
-                const int64_t idx = (int64_t)py * Ws + px;
+                const int64_t idx = (int64_t)(py - r0) * Ws + px;
                 if (winner[idx] >= 0) continue;
                 double d[3];
                 camera_ray(&cam, Ws, Hs, px, py, d);
@@ -428,9 +447,9 @@ int synth_frags_camera(const synth_scene *sc, uint64_t seed, int Ws, int Hs, dou
     }
 
     int status = 0;
-    for (int py = 0; py < Hs; ++py) {
+    for (int py = r0; py < r1; ++py) {
         for (int px = 0; px < Ws; ++px) {
-            const int64_t idx = (int64_t)py * Ws + px;
+            const int64_t idx = (int64_t)(py - r0) * Ws + px;
             double d[3];
             camera_ray(&cam, Ws, Hs, px, py, d);
             double u, v, z;

@@ -29,7 +29,9 @@ def lib():
 def test_header_declares_the_entry_points():
     names = _declared_functions()
     for want in ("rbsm_visibility", "rsmss_visibility", "sm_visibility", "rbsm_footprint",
-                 "rbsm_last_error", "rbsm_abi_version", "rbsm_pass_tuned", "rbsm_default_tuning"):
+                 "rbsm_last_error", "rbsm_abi_version", "rbsm_pass_tuned", "rbsm_default_tuning",
+                 "rbsm_plan_create", "rbsm_plan_launch", "rbsm_plan_update", "rbsm_plan_autotune",
+                 "rbsm_plan_capture", "rbsm_plan_destroy"):
         assert want in names, names
 
 
@@ -96,3 +98,22 @@ def test_tuning_validated_on_host(lib):
     for bad in (rb.RbsmTuning(24, 1, 4096), rb.RbsmTuning(32, 0, 4096), rb.RbsmTuning(32, 1, 100000)):
         assert lib.rbsm_pass_tuned(0, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(bad), 0x200000, None) == -1
     assert lib.rbsm_pass_tuned(3, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(d), 0x200000, None) == -1
+
+
+def test_plan_rejects_bad_jobs_on_host(lib):
+    import paper_1711_07793_amd as rb
+    h = ctypes.c_void_p()
+    p = _p()
+    jobs = (rb.RbsmJob * 2)()
+    jobs[0] = rb.RbsmJob(0x1000000, 0x2000000, 64, p, 0, 0x3000000)
+    jobs[1] = rb.RbsmJob(0x1000000, 0x2000000, 64, p, 5, 0x3100000)  # bad mode
+    assert lib.rbsm_plan_create(jobs, 2, None, ctypes.byref(h)) == -1 and not h.value
+    jobs[1] = rb.RbsmJob(0x1000000, 0x2000000, 64, p, 0, 0x3000010)  # outputs overlap
+    assert lib.rbsm_plan_create(jobs, 2, None, ctypes.byref(h)) == -1
+    assert "overlap" in lib.rbsm_last_error().decode()
+    q = _p(kernel_radius=2)
+    jobs[1] = rb.RbsmJob(0x1000000, 0x2000000, 64, q, 1, 0x3100000)  # radius > 0 not batched
+    assert lib.rbsm_plan_create(jobs, 2, None, ctypes.byref(h)) == -1
+    assert lib.rbsm_plan_create(jobs, 0, None, ctypes.byref(h)) == -1
+    assert lib.rbsm_plan_launch(None, None) == -1
+    assert lib.rbsm_plan_fragments(None) == -1
