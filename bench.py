@@ -32,12 +32,14 @@ sys.path.insert(0, ROOT)
 METRIC = "shaded fragments/sec (RBSM, RSMSS) batched vs plain per-view; p99 frame latency"
 PEAK_HBM_GBPS = 8000.0
 ROTATE_BYTES = 512 << 20
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "hard_kernel_tri64_map2048_1080p_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "tile_kernel_hard_tri64_map2048_1080p_traffic.md")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the hard-pass kernel (tile pass and the
+    per-fragment device helpers)."""
     h = hashlib.sha256()
-    for rel in ("paper_1711_07793_amd/csrc/rbsm.hip", "paper_1711_07793_amd/csrc/rbsm_device.hpp"):
+    for rel in ("paper_1711_07793_amd/csrc/tile_pass.hpp", "paper_1711_07793_amd/csrc/rbsm_device.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -84,8 +86,11 @@ class Frames:
 
 
 def time_pass(torch, rb, lib, fn_name, frames: Frames, params, steps: int, warmup: int):
-    """Warm up, then time exactly `steps` launches (synchronised on both sides)
-    with a HIP event pair around every launch on the launch stream."""
+    """Warm up, then time exactly `steps` back-to-back launches, synchronised on
+    both sides.  One HIP event pair on the launch stream brackets the timed
+    region, so the average launch duration is the event time over `steps`
+    (kernel time plus the back-to-back dispatch gap, nothing from the host).
+    Returns (wall seconds, average launch ms, slot index of every step)."""
     p = rb.Params(**params).to_c()
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
@@ -96,19 +101,39 @@ def time_pass(torch, rb, lib, fn_name, frames: Frames, params, steps: int, warmu
         a = args[k % nslot]
         st = fn(a[0], a[1], a[2], a[3], a[4], sh)
         assert st == 0, rb.rbsm_last_error()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     for k in range(steps):
         a = args[k % nslot]
-        ev[k][0].record(stream)
         fn(a[0], a[1], a[2], a[3], a[4], sh)
-        ev[k][1].record(stream)
+    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dur_ms = np.array([s.elapsed_time(e) for s, e in ev])
-    used = [args_idx % nslot for args_idx in range(steps)]
-    return wall, dur_ms, used
+    avg_ms = ev0.elapsed_time(ev1) / steps
+    used = [k % nslot for k in range(steps)]
+    return wall, avg_ms, used
+
+
+def launch_latency(torch, rb, lib, fn_name, frames: Frames, params, count: int):
+    """Per-frame latency: `count` single launches, each bracketed by its own
+    event pair and synchronised before the next (dispatch included)."""
+    p = rb.Params(**params).to_c()
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    fn = getattr(lib, fn_name)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat = []
+    for k in range(count):
+        sl = frames.slots[k % len(frames.slots)]
+        s0.record(stream)
+        fn(sl[1].data_ptr(), sl[2].data_ptr(), frames.n, ctypes.byref(p), sl[3].data_ptr(), sh)
+        s1.record(stream)
+        s1.synchronize()
+        lat.append(s0.elapsed_time(s1))
+    lat = np.array(lat)
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
 
 def algorithmic_bytes(torch, rb, frames: Frames, params, mode: int, out_bytes: int):
@@ -137,6 +162,76 @@ def copy_bandwidth(torch, nbytes: int = 256 << 20, reps: int = 5) -> float:
     e.record()
     torch.cuda.synchronize()
     return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+
+
+def batched_section(torch, rb, frames_timed: int = 20):
+    """The batched workload (16 maps, 8 views, 48 jobs of uneven size) run as
+    plain per-view launches (one call per job, frame-synchronised), as one
+    batched launch per frame, and as one graph replay per frame."""
+    import synth
+    w = synth.make_batched(4001)
+    maps = [torch.from_numpy(m).cuda() for m in w["maps"]]
+    jobs = []
+    for j in w["jobs"]:
+        f = torch.from_numpy(j["frags"]).cuda()
+        out = torch.empty(len(j["frags"]), dtype=torch.uint8 if j["mode"] == 0 else torch.float32, device="cuda")
+        jobs.append(dict(map=maps[j["map"]], frags=f, params=j["params"], mode=j["mode"], out=out))
+    n_frag = sum(j["frags"].numel() // 3 for j in jobs)
+    lib = rb.load_library()
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    cparams = [rb.Params(**j["params"]).to_c() for j in jobs]
+
+    def plain_frame():
+        for j, p in zip(jobs, cparams):
+            fn = lib.rbsm_visibility if j["mode"] == 0 else lib.rsmss_visibility
+            st = fn(j["map"].data_ptr(), j["frags"].data_ptr(), j["frags"].numel() // 3, ctypes.byref(p),
+                    j["out"].data_ptr(), sh)
+            assert st == 0, rb.rbsm_last_error()
+
+    def run(frame_fn, sync_fn):
+        for _ in range(3):
+            frame_fn()
+        sync_fn()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(frames_timed):
+            a = time.perf_counter()
+            frame_fn()
+            sync_fn()
+            lat.append((time.perf_counter() - a) * 1e3)
+        wall = time.perf_counter() - t0
+        lat = np.array(lat)
+        return {"fragments_per_s": n_frag * frames_timed / wall, "p50_frame_ms": float(np.percentile(lat, 50)),
+                "p99_frame_ms": float(np.percentile(lat, 99))}
+
+    plain = run(plain_frame, torch.cuda.synchronize)
+    want = [j["out"].clone() for j in jobs]
+    plan = rb.Plan(jobs)
+    tune = plan.autotune(reps=3)
+    for j in jobs:
+        j["out"].fill_(0)
+    plan.launch()
+    torch.cuda.synchronize()
+    equal = all(torch.equal(j["out"], wv) for j, wv in zip(jobs, want))
+    batched = run(plan.launch, torch.cuda.synchronize)
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    plan.capture(s)
+    graph = run(lambda: plan.launch(s), s.synchronize)
+    plan.close()
+    return {
+        "workload": "16 maps (cascades 8192^2..1024^2 + 12 spot maps 1024^2..4096^2), 8 views 720p..4K, "
+                    f"{len(jobs)} jobs (cascades hard, spots RSMSS r=0)",
+        "fragments_per_frame": n_frag,
+        "plain_per_view": plain,
+        "batched": batched,
+        "batched_graph": graph,
+        "speedup_vs_plain": batched["fragments_per_s"] / plain["fragments_per_s"],
+        "graph_speedup_vs_plain": graph["fragments_per_s"] / plain["fragments_per_s"],
+        "tuning": {"tile_w": tune.tile_w, "apron": tune.apron, "lds_cap": tune.lds_cap},
+        "bitwise_equal_to_plain": bool(equal),
+    }
 
 
 def cpu_baseline(frames: Frames, budget_s: float):
@@ -183,13 +278,14 @@ def main():
     # ---- headline: hard RBSM, 2048^2 map, 1920x1080 fragments -----------
     frames = Frames(torch, 2, [2001, 2002, 2003, 2004, 2005], ROTATE_BYTES, "hard", torch.uint8)
     params = frames.params
-    wall, dur, used = time_pass(torch, rb, lib, "rbsm_visibility", frames, params, args.steps, args.warmup)
+    wall, avg_kernel_ms, used = time_pass(torch, rb, lib, "rbsm_visibility", frames, params, args.steps,
+                                          args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     value = frames.n * args.steps / wall
     per_frame_bytes = algorithmic_bytes(torch, rb, frames, params, 0, 1)
     slot_scene = [s[0] for s in frames.slots]
     bytes_per_launch = float(np.mean([per_frame_bytes[slot_scene[u]] for u in used]))
-    avg_kernel_ms = float(dur.mean())
+    p50_ms, p99_ms = launch_latency(torch, rb, lib, "rbsm_visibility", frames, params, 500)
     achieved = bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
     traffic = read_traffic(khash)
@@ -215,7 +311,7 @@ def main():
             "resident_bytes": frames.bytes_resident,
         },
         "roofline": {
-            "kernel": "hard_kernel",
+            "kernel": "tile_kernel<true, 32> (hard pass)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBPS,
@@ -226,8 +322,8 @@ def main():
             "avg_kernel_ms": avg_kernel_ms,
             "kernel_source_sha": khash,
         },
-        "p50_frame_ms": float(np.percentile(dur, 50)),
-        "p99_frame_ms": float(np.percentile(dur, 99)),
+        "p50_frame_ms": p50_ms,
+        "p99_frame_ms": p99_ms,
     }
 
     if args.copy_calibration or not args.no_extras:
@@ -235,16 +331,16 @@ def main():
 
     if not args.no_extras:
         # plain shadow mapping of the same frames (the paper's baseline pass)
-        w_sm, d_sm, _ = time_pass(torch, rb, lib, "sm_visibility", frames, params, max(200, args.steps // 4), 20)
+        w_sm, a_sm, _ = time_pass(torch, rb, lib, "sm_visibility", frames, params, max(200, args.steps // 4), 20)
         out["plain_sm"] = {"fragments_per_s": frames.n * max(200, args.steps // 4) / w_sm,
-                           "avg_kernel_ms": float(d_sm.mean())}
+                           "avg_kernel_ms": a_sm}
         del frames
         torch.cuda.empty_cache()
         # RSMSS at 3840x2160 on a 4096^2 fenced scene, radius 0 (Listing 5 exactly)
         fr3 = Frames(torch, 3, [3001, 3002, 3003], ROTATE_BYTES, "rsmss", torch.float32)
         p3 = dict(fr3.params, kernel_radius=0)
         steps3 = max(100, args.steps // 10)
-        w3, d3, used3 = time_pass(torch, rb, lib, "rsmss_visibility", fr3, p3, steps3, 10)
+        w3, a3, used3 = time_pass(torch, rb, lib, "rsmss_visibility", fr3, p3, steps3, 10)
         b3 = algorithmic_bytes(torch, rb, fr3, p3, 1, 4)
         sc3 = [s[0] for s in fr3.slots]
         bpl3 = float(np.mean([b3[sc3[u]] for u in used3]))
@@ -253,10 +349,14 @@ def main():
                         "MAXDIST 16",
             "fragments_per_s": fr3.n * steps3 / w3,
             "ms_per_step": w3 * 1e3 / steps3,
-            "avg_kernel_ms": float(d3.mean()),
-            "achieved_GBps": bpl3 / (float(d3.mean()) * 1e-3) / 1e9,
+            "avg_kernel_ms": a3,
+            "achieved_GBps": bpl3 / (a3 * 1e-3) / 1e9,
             "algorithmic_bytes_per_launch": bpl3,
         }
+        del fr3
+        torch.cuda.empty_cache()
+        out["batched"] = batched_section(torch, rb)
+        torch.cuda.empty_cache()
         frames = Frames.__new__(Frames)  # host frames for the CPU leg
         import synth
         frames.host = [synth.make_config(2, s) for s in (2001, 2002, 2003, 2004, 2005)]

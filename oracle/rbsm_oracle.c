@@ -37,6 +37,9 @@
  *  - RPCF (radius r > 0): box average of the RSMSS value evaluated at the
  *    (2r+1)^2 texels around the fragment's texel with the same sub-texel
  *    position and depth (Sec. 5.3 suggests PCF to suppress skeleton artifacts).
+ *    The paper fixes no summation order or precision, so the average is the
+ *    plain definition: terms summed in binary64 (exact for these values in
+ *    practice), divided by (2r+1)^2 in binary64, rounded to binary32 once.
  */
 #include <math.h>
 #include <stdint.h>
@@ -285,7 +288,7 @@ int oracle_rsmss(const float *map, const float *frags, int64_t n, const oracle_p
                  float *out) {
     if (!params_ok(p)) return -1;
     const int r = p->kernel_radius;
-    const float inv = 1.0f / (float)((2 * r + 1) * (2 * r + 1));
+    const double count = (double)((2 * r + 1) * (2 * r + 1));
     for (int64_t k = 0; k < n; ++k) {
         const float *f = frags + 3 * k;
         if (!frag_ok(p, f)) return -2;
@@ -298,13 +301,13 @@ int oracle_rsmss(const float *map, const float *frags, int64_t n, const oracle_p
             out[k] = det.vis;
             continue;
         }
-        float sum = 0.0f;
+        double sum = 0.0;
         for (int a = -r; a <= r; ++a)
             for (int b = -r; b <= r; ++b) {
                 rbsm_at(map, p, i0 + a, j0 + b, fx, fy, pz, 0, &det);
-                sum += det.vis;
+                sum += (double)det.vis;
             }
-        out[k] = sum * inv;
+        out[k] = (float)(sum / count);
     }
     return 0;
 }

@@ -92,6 +92,45 @@ def test_rpcf_full_size_sampled(rb):
     check_soft(c["map"], c["frags"], p, got, idx)
 
 
+@pytest.mark.parametrize("r,max_dist", [(1, 1), (1, 16), (3, 16), (7, 16), (15, 16), (2, 29), (30, 1),
+                                        (2, 40), (6, 64)])
+def test_rpcf_radii_and_reach(rb, r, max_dist):
+    """Every RPCF route: staged box (screen tiles), words from global memory
+    (box too large), and the per-term form when r + MAXDIST exceeds a word."""
+    c = synth.make_config(3, 3005, small=True)
+    n = len(c["frags"])
+    idx = np.arange(0, n, max(1, n // (4000 if r <= 7 else 800)))
+    p = dict(c["params"], kernel_radius=r, max_dist=max_dist)
+    say(f"rpcf r={r} maxd={max_dist} n={n}")
+    got = rb.rsmss_visibility(dev(c["map"]), dev(c["frags"]), p).cpu().numpy()
+    check_soft(c["map"], c["frags"], p, got, idx)
+    assert np.all((got >= 0) & (got <= 1))
+
+
+@pytest.mark.parametrize("vw", [0, 97])
+def test_rpcf_flat_and_scattered_fragments(rb, vw):
+    """Uniform random fragments: tile boxes are far larger than LDS, so words
+    come from global memory; view_width 97 makes ragged 2-D tiles."""
+    c = synth.make_config(1, 1009, small=True)
+    f = np.ascontiguousarray(c["frags"][:6001])
+    for r in (1, 4):
+        p = dict(c["params"], kernel_radius=r, view_width=vw)
+        got = rb.rsmss_visibility(dev(c["map"]), dev(f), p).cpu().numpy()
+        check_soft(c["map"], f, p, got)
+
+
+def test_rpcf_clamped_edges_of_tiny_maps(rb):
+    """Boxes that hang over every map border (clamp-to-edge reads)."""
+    rng = np.random.default_rng(8)
+    for (H, W) in [(1, 1), (3, 2), (9, 17), (40, 33)]:
+        m = np.where(rng.random((H, W)) < 0.4, 0.5, 0.9).astype(np.float32)
+        f = _frags_for(W, H, 3000 + W, seed=W, spill=0.2)
+        for r, vw in ((2, 0), (5, 50)):
+            p = dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=12, kernel_radius=r, view_width=vw)
+            got = rb.rsmss_visibility(dev(m), dev(f), p).cpu().numpy()
+            check_soft(m, f, p, got)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_footprint_matches_oracle_reads(rb, mode):
     c = synth.make_config(2, 2001, small=True)
