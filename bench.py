@@ -353,6 +353,19 @@ def main():
             "achieved_GBps": bpl3 / (a3 * 1e-3) / 1e9,
             "algorithmic_bytes_per_launch": bpl3,
         }
+        # RPCF at the light's own kernel radius (the same frames)
+        r3 = fr3.host[0]["light_radius"]
+        pr = dict(fr3.params, kernel_radius=r3)
+        steps_r = max(20, args.steps // 100)
+        wr, ar, _ = time_pass(torch, rb, lib, "rsmss_visibility", fr3, pr, steps_r, 3)
+        out["rpcf"] = {
+            "workload": f"RPCF radius {r3} ({(2 * r3 + 1) ** 2} RSMSS terms per fragment) on the RSMSS frames",
+            "kernel_radius": r3,
+            "fragments_per_s": fr3.n * steps_r / wr,
+            "ms_per_step": wr * 1e3 / steps_r,
+            "avg_kernel_ms": ar,
+            "terms_per_s": fr3.n * (2 * r3 + 1) ** 2 / (ar * 1e-3),
+        }
         del fr3
         torch.cuda.empty_cache()
         out["batched"] = batched_section(torch, rb)
