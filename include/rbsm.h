@@ -193,10 +193,97 @@ int64_t rbsm_plan_fragments(const rbsm_plan *plan);
 
 void rbsm_plan_destroy(rbsm_plan *plan);
 
+/*
+ * Multi-light compositing: one shadow value per fragment of a view lit by
+ * several lights, the weighted sum of the per-light visibilities,
+ *   out[k] = sum over l in order of weights[l] * vis_l[k]
+ * in binary32 (each product rounded, then added).  The visibility function
+ * scales one light's contribution (Listing 1); how several lights combine is
+ * not in the paper, so the weights are the caller's per-light intensities.
+ *   n          fragments, >= 0 (0 is a no-op)
+ *   n_lights   1..8
+ *   vis        host array of n_lights DEVICE pointers: uint8_t[n] masks from
+ *              rbsm_visibility (modes[l] = 0) or float[n] from
+ *              rsmss_visibility (modes[l] = 1)
+ *   modes, weights  host arrays of n_lights
+ *   out        device float[n]; must not overlap any vis array
+ */
+int rbsm_composite(int64_t n, int32_t n_lights, const void *const *vis, const int32_t *modes, const float *weights,
+                   float *out, hipStream_t stream);
+
+/*
+ * Serving engine: continuous batching of shadow requests over resident maps.
+ *
+ * An engine owns one device arena of hbm_budget_bytes, allocated at creation
+ * (the only device allocation it makes), two streams and a scheduler thread.
+ * A request is one view: its light-space fragments for 1..8 registered
+ * lights (device memory, owned by the caller and left untouched until the
+ * request completes), plus host buffers for the results.  The engine admits
+ * requests first come, first served while their result buffers fit in the
+ * arena and fewer than max_inflight requests are admitted; each scheduling
+ * step runs one batched pass over the jobs of every admitted request (each
+ * per-light result is bitwise the plain entry point's), the RPCF jobs, and
+ * one compositing launch, then copies results to the host buffers on a second
+ * stream while the next step computes.  Requests that arrive while others run
+ * join the next step.  Results are the same alone and in any mix.
+ */
+typedef struct rbsm_engine rbsm_engine;  /* opaque */
+
+typedef struct {
+    int32_t light;         /* id from rbsm_engine_add_light */
+    int32_t mode;          /* 0: hard (rbsm_visibility), 1: RSMSS / RPCF (rsmss_visibility) */
+    const float *frags;    /* device [3*n] light-space (u, v, z) for this light */
+    float depth_bias;
+    int32_t max_dist;      /* 1..64 */
+    int32_t kernel_radius; /* mode 1 only, 0..32 */
+    float weight;          /* this light's weight in the composite */
+    void *out_host;        /* host uint8_t[n] (mode 0) or float[n] (mode 1) for this
+                              light's result, or NULL; pinned memory overlaps best */
+} rbsm_request_light;
+
+typedef struct {
+    int64_t n;             /* fragments of the view, 0..2^31-1 */
+    int32_t view_width;    /* layout hint as in rbsm_params */
+    int32_t n_lights;      /* 1..8 */
+    rbsm_request_light lights[8];
+    float *composite_host; /* host float[n] for the composite, or NULL */
+} rbsm_request;
+
+typedef struct {
+    int64_t submitted, completed, queued, inflight;
+    int64_t launches, jobs_launched;  /* scheduling steps, (request, light) jobs */
+    int64_t fragments_completed;      /* sum over completed requests of n * n_lights */
+    int64_t arena_bytes, arena_peak_bytes;
+} rbsm_engine_stats;
+
+/* Create an engine on the current device.  hbm_budget_bytes >= 4096,
+ * max_inflight 1..4096. */
+int rbsm_engine_create(int64_t hbm_budget_bytes, int32_t max_inflight, rbsm_engine **engine);
+
+/* Register a resident shadow map (device, caller-owned, row-major with pitch;
+ * must stay valid while the engine uses it).  Writes its id. */
+int rbsm_engine_add_light(rbsm_engine *engine, const float *shadow_map, int32_t width, int32_t height, int64_t pitch,
+                          int32_t *light_id);
+
+/* Queue a request (copied; the arrays it points to are not).  Rejected when
+ * its result buffers alone exceed the budget.  Writes a ticket. */
+int rbsm_engine_submit(rbsm_engine *engine, const rbsm_request *request, int64_t *ticket);
+
+/* Wait up to timeout_ms (< 0: forever) for a ticket.  Returns 1 when its
+ * results are in the host buffers (the ticket is then forgotten and
+ * *latency_ms, if non-NULL, is submit-to-completion time), 0 on time-out, a
+ * negative code on failure. */
+int rbsm_engine_wait(rbsm_engine *engine, int64_t ticket, int32_t timeout_ms, double *latency_ms);
+
+int rbsm_engine_get_stats(rbsm_engine *engine, rbsm_engine_stats *stats);
+
+/* Finish every queued request, stop the scheduler and free the engine. */
+void rbsm_engine_destroy(rbsm_engine *engine);
+
 /* Message for the calling thread's last non-zero return ("" if none). */
 const char *rbsm_last_error(void);
 
-/* ABI version: 100 * major + minor. */
+/* ABI version: 100 * major + minor (1.01: compositing and the serving engine). */
 int32_t rbsm_abi_version(void);
 
 #ifdef __cplusplus

@@ -69,6 +69,8 @@ def _load():
     lib.oracle_set_touch.restype = None
     lib.oracle_fetch_count.argtypes = []
     lib.oracle_fetch_count.restype = ctypes.c_int64
+    lib.oracle_composite.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp]
+    lib.oracle_composite.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -173,3 +175,21 @@ def touched_texels(map_: np.ndarray, frags: np.ndarray, params: dict, hard: bool
     finally:
         lib.oracle_set_touch(None)
     return touch, reads
+
+
+def composite(vis: list, weights) -> np.ndarray:
+    """Multi-light compositing: float32 [N] = sum over lights in order of
+    weight * visibility (binary32 products, then sums).  Each entry of ``vis``
+    is a uint8 hard mask or a float32 visibility array of the same length."""
+    arrs = [np.ascontiguousarray(v) for v in vis]
+    n = arrs[0].shape[0] if arrs else 0
+    if not 1 <= len(arrs) <= 8 or any(a.shape != (n,) for a in arrs):
+        raise ValueError("composite: need 1..8 arrays of one length")
+    hard = np.array([1 if a.dtype == np.uint8 else 0 for a in arrs], np.int32)
+    arrs = [a if a.dtype == np.uint8 else a.astype(np.float32) for a in arrs]
+    w = np.ascontiguousarray(weights, np.float32)
+    ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    out = np.empty(n, np.float32)
+    _check(_load().oracle_composite(n, len(arrs), ptrs, hard.ctypes.data, w.ctypes.data, out.ctypes.data),
+           "composite")
+    return out

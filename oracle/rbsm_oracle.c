@@ -389,3 +389,26 @@ double oracle_margin_one(const float *map, const float *frag, const oracle_param
     g_touch = saved;
     return m;
 }
+
+/* Multi-light compositing (serving extension): the per-fragment weighted sum
+ * of per-light visibilities, out[k] = sum over lights in order of
+ * weights[l] * vis_l[k], each product rounded to binary32, then added.  The
+ * visibility scales one light's contribution (Listing 1); how lights combine
+ * is not in the paper, so the weights are per-light intensities.  vis[l] is a
+ * uint8 mask (hard[l] != 0) or a float visibility. */
+int oracle_composite(int64_t n, int n_lights, const void *const *vis, const int32_t *hard, const float *weights,
+                     float *out) {
+    if (n < 0 || n_lights < 1 || n_lights > 8) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        float acc = 0.0f;
+        for (int l = 0; l < n_lights; ++l) {
+            float v;
+            if (hard[l]) v = (float)((const uint8_t *)vis[l])[k];
+            else v = ((const float *)vis[l])[k];
+            const float term = weights[l] * v;
+            acc = acc + term;
+        }
+        out[k] = acc;
+    }
+    return 0;
+}

@@ -56,6 +56,26 @@ class RbsmJob(ctypes.Structure):
                 ("params", RbsmParams), ("mode", ctypes.c_int32), ("out", ctypes.c_void_p)]
 
 
+class RbsmRequestLight(ctypes.Structure):
+    """Mirror of ``rbsm_request_light``."""
+    _fields_ = [("light", ctypes.c_int32), ("mode", ctypes.c_int32), ("frags", ctypes.c_void_p),
+                ("depth_bias", ctypes.c_float), ("max_dist", ctypes.c_int32), ("kernel_radius", ctypes.c_int32),
+                ("weight", ctypes.c_float), ("out_host", ctypes.c_void_p)]
+
+
+class RbsmRequest(ctypes.Structure):
+    """Mirror of ``rbsm_request``."""
+    _fields_ = [("n", ctypes.c_int64), ("view_width", ctypes.c_int32), ("n_lights", ctypes.c_int32),
+                ("lights", RbsmRequestLight * 8), ("composite_host", ctypes.c_void_p)]
+
+
+class RbsmEngineStats(ctypes.Structure):
+    """Mirror of ``rbsm_engine_stats``."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "queued", "inflight", "launches",
+                                              "jobs_launched", "fragments_completed", "arena_bytes",
+                                              "arena_peak_bytes")]
+
+
 class RbsmError(RuntimeError):
     pass
 
@@ -102,6 +122,20 @@ def load_library() -> ctypes.CDLL:
     lib.rbsm_plan_fragments.restype = ctypes.c_int64
     lib.rbsm_plan_destroy.argtypes = [vp]
     lib.rbsm_plan_destroy.restype = None
+    lib.rbsm_composite.argtypes = [i64, ctypes.c_int32, vp, vp, vp, vp, vp]
+    lib.rbsm_composite.restype = ctypes.c_int
+    lib.rbsm_engine_create.argtypes = [i64, ctypes.c_int32, PP]
+    lib.rbsm_engine_create.restype = ctypes.c_int
+    lib.rbsm_engine_add_light.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.rbsm_engine_add_light.restype = ctypes.c_int
+    lib.rbsm_engine_submit.argtypes = [vp, ctypes.POINTER(RbsmRequest), ctypes.POINTER(ctypes.c_int64)]
+    lib.rbsm_engine_submit.restype = ctypes.c_int
+    lib.rbsm_engine_wait.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.rbsm_engine_wait.restype = ctypes.c_int
+    lib.rbsm_engine_get_stats.argtypes = [vp, ctypes.POINTER(RbsmEngineStats)]
+    lib.rbsm_engine_get_stats.restype = ctypes.c_int
+    lib.rbsm_engine_destroy.argtypes = [vp]
+    lib.rbsm_engine_destroy.restype = None
     lib.rbsm_last_error.argtypes = []
     lib.rbsm_last_error.restype = ctypes.c_char_p
     lib.rbsm_abi_version.argtypes = []
@@ -300,5 +334,116 @@ class Plan:
         self.close()
 
 
-__all__ = ["Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+def rbsm_composite(vis: list, modes: list, weights: list, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Weighted sum of per-light visibilities (device tensors: uint8 masks for
+    mode 0, float32 for mode 1) into one float32 tensor."""
+    if not 1 <= len(vis) <= 8 or len(modes) != len(vis) or len(weights) != len(vis):
+        raise RbsmError("rbsm_composite: need 1..8 lights with one mode and weight each")
+    n = vis[0].numel()
+    for v, m in zip(vis, modes):
+        if v.device.type != "cuda" or v.numel() != n or not v.is_contiguous():
+            raise RbsmError("rbsm_composite: visibilities must be contiguous device tensors of one length")
+        if v.dtype != (torch.uint8 if m == 0 else torch.float32):
+            raise RbsmError("rbsm_composite: mode 0 needs uint8, mode 1 float32")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=vis[0].device)
+    ptrs = (ctypes.c_void_p * len(vis))(*[v.data_ptr() for v in vis])
+    md = (ctypes.c_int32 * len(vis))(*modes)
+    w = (ctypes.c_float * len(vis))(*weights)
+    _call("rbsm_composite", n, len(vis), ptrs, md, w, out.data_ptr(), _stream(stream))
+    return out
+
+
+class Engine:
+    """Serving engine (``rbsm_engine_*``): continuous batching of shadow
+    requests over resident shadow maps, admitted by an HBM budget.
+
+    ``submit`` takes one view: ``n`` fragments, a layout hint and 1..8
+    lights, each ``dict(light=id, mode=0|1, frags=<device float32 [n, 3]>,
+    depth_bias=, max_dist=, kernel_radius=, weight=, out=<host tensor or
+    None>)``, plus an optional host float32 ``composite`` tensor.  Host
+    tensors should be pinned.  The tensors are kept alive until ``wait``
+    returns for that ticket.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 64):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        st = self._lib.rbsm_engine_create(int(hbm_budget_bytes), int(max_inflight), ctypes.byref(self._h))
+        if st != RBSM_OK:
+            raise RbsmError(rbsm_last_error())
+        self._keep = {}
+        self._maps = []
+
+    def add_light(self, shadow_map: torch.Tensor) -> int:
+        if shadow_map.device.type != "cuda" or shadow_map.dtype != torch.float32 or shadow_map.dim() != 2 \
+                or shadow_map.stride(1) != 1:
+            raise RbsmError("add_light: need a 2-D float32 device tensor with contiguous rows")
+        lid = ctypes.c_int32()
+        st = self._lib.rbsm_engine_add_light(self._h, shadow_map.data_ptr(), shadow_map.shape[1],
+                                             shadow_map.shape[0], shadow_map.stride(0), ctypes.byref(lid))
+        if st != RBSM_OK:
+            raise RbsmError(rbsm_last_error())
+        self._maps.append(shadow_map)
+        return int(lid.value)
+
+    def submit(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None) -> int:
+        if not 1 <= len(lights) <= 8:
+            raise RbsmError("submit: need 1..8 lights")
+        q = RbsmRequest()
+        q.n, q.view_width, q.n_lights = int(n), int(view_width), len(lights)
+        keep = [composite]
+        for i, L in enumerate(lights):
+            f = L["frags"]
+            if f.device.type != "cuda" or f.dtype != torch.float32 or not f.is_contiguous() or f.numel() != 3 * n:
+                raise RbsmError("submit: frags must be contiguous float32 device tensors of n triples")
+            out = L.get("out")
+            if out is not None:
+                want = torch.uint8 if L.get("mode", 0) == 0 else torch.float32
+                if out.device.type != "cpu" or out.dtype != want or out.numel() != n or not out.is_contiguous():
+                    raise RbsmError("submit: out must be a contiguous host tensor of n results of the mode's type")
+            q.lights[i] = RbsmRequestLight(int(L["light"]), int(L.get("mode", 0)), f.data_ptr(),
+                                           float(L.get("depth_bias", 0.0)), int(L.get("max_dist", 16)),
+                                           int(L.get("kernel_radius", 0)), float(L.get("weight", 1.0)),
+                                           out.data_ptr() if out is not None else None)
+            keep += [f, out]
+        if composite is not None:
+            if composite.device.type != "cpu" or composite.dtype != torch.float32 or composite.numel() != n:
+                raise RbsmError("submit: composite must be a host float32 tensor of n values")
+            q.composite_host = composite.data_ptr()
+        t = ctypes.c_int64()
+        st = self._lib.rbsm_engine_submit(self._h, ctypes.byref(q), ctypes.byref(t))
+        if st != RBSM_OK:
+            raise RbsmError(rbsm_last_error())
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """Latency in ms (submit to results on the host), or None on time-out."""
+        ms = ctypes.c_double()
+        st = self._lib.rbsm_engine_wait(self._h, int(ticket), int(timeout_ms), ctypes.byref(ms))
+        if st == 0:
+            return None
+        self._keep.pop(int(ticket), None)
+        if st < 0:
+            raise RbsmError(rbsm_last_error())
+        return float(ms.value)
+
+    def stats(self) -> dict:
+        s = RbsmEngineStats()
+        if self._lib.rbsm_engine_get_stats(self._h, ctypes.byref(s)) != RBSM_OK:
+            raise RbsmError(rbsm_last_error())
+        return {f: int(getattr(s, f)) for f, _ in RbsmEngineStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.rbsm_engine_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._keep = {}
+
+    def __del__(self):
+        self.close()
+
+
+__all__ = ["Engine", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
            "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

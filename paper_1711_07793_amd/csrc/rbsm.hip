@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <vector>
 
@@ -280,6 +281,8 @@ void launch_batch(const rbsm_plan *p, hipStream_t stream) {
 
 }  // namespace
 
+#include "serve.hpp"
+
 extern "C" {
 
 int rbsm_visibility(const float *shadow_map, const float *frags, int64_t n, const rbsm_params *p,
@@ -491,8 +494,194 @@ void rbsm_plan_destroy(rbsm_plan *plan) {
     delete plan;
 }
 
+int rbsm_composite(int64_t n, int32_t n_lights, const void *const *vis, const int32_t *modes, const float *weights,
+                   float *out, hipStream_t stream) {
+    const char *fn = "rbsm_composite";
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(RBSM_ERR_INVALID_ARG, "%s: n must be in 0..2^31-1", fn);
+    if (n_lights < 1 || n_lights > rbsm::kMaxLights) return fail(RBSM_ERR_INVALID_ARG, "%s: n_lights must be 1..8", fn);
+    if (!vis || !modes || !weights) return fail(RBSM_ERR_INVALID_ARG, "%s: null host array", fn);
+    if (n == 0) return RBSM_OK;
+    if (!out) return fail(RBSM_ERR_INVALID_ARG, "%s: out is null", fn);
+    rbsm::CompJob J{};
+    J.n_lights = n_lights;
+    J.n = n;
+    J.out = out;
+    for (int l = 0; l < n_lights; ++l) {
+        if (modes[l] != 0 && modes[l] != 1) return fail(RBSM_ERR_INVALID_ARG, "%s: modes must be 0 or 1", fn);
+        if (!vis[l]) return fail(RBSM_ERR_INVALID_ARG, "%s: null visibility pointer", fn);
+        if (overlaps(out, (size_t)n * 4u, vis[l], (size_t)n * (modes[l] == 0 ? 1u : 4u)))
+            return fail(RBSM_ERR_INVALID_ARG, "%s: out overlaps an input", fn);
+        J.vis[l] = vis[l];
+        J.w[l] = weights[l];
+        J.hard[l] = modes[l] == 0;
+    }
+    hipLaunchKernelGGL(rbsm::composite_kernel, dim3((unsigned)rbsm::composite_blocks(n)), dim3(rbsm::kCompT), 0,
+                       stream, J);
+    return launched(fn);
+}
+
+int rbsm_engine_create(int64_t hbm_budget_bytes, int32_t max_inflight, rbsm_engine **engine) {
+    const char *fn = "rbsm_engine_create";
+    if (!engine) return fail(RBSM_ERR_INVALID_ARG, "%s: engine is null", fn);
+    *engine = nullptr;
+    if (hbm_budget_bytes < 4096) return fail(RBSM_ERR_INVALID_ARG, "%s: budget below 4096 bytes", fn);
+    if (max_inflight < 1 || max_inflight > 4096) return fail(RBSM_ERR_INVALID_ARG, "%s: max_inflight must be 1..4096", fn);
+    rbsm_engine *E = new (std::nothrow) rbsm_engine;
+    if (!E) return fail(RBSM_ERR_INVALID_ARG, "%s: out of host memory", fn);
+    E->max_inflight = max_inflight;
+    hipError_t e = hipGetDevice(&E->device);
+    if (e == hipSuccess) e = hipMalloc(&E->d_arena, (size_t)hbm_budget_bytes);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->s_compute, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->s_copy, hipStreamNonBlocking);
+    for (int s = 0; s < rbsm::kServeSlots && e == hipSuccess; ++s) {
+        Slot &S = E->slots[s];
+        e = hipMalloc(&S.d_jobs, sizeof(JobDev) * rbsm::kServeMaxJobs);
+        if (e == hipSuccess) e = hipMalloc(&S.d_comp, sizeof(rbsm::CompJob) * rbsm::kServeMaxReqs);
+        if (e == hipSuccess) e = hipHostMalloc(&S.h_jobs, sizeof(JobDev) * rbsm::kServeMaxJobs, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(&S.h_comp, sizeof(rbsm::CompJob) * rbsm::kServeMaxReqs, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&S.compute_done, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        rbsm_engine_destroy(E);
+        return fail(RBSM_ERR_HIP, "%s: could not allocate the arena, streams or tables", fn);
+    }
+    E->arena.reset(hbm_budget_bytes);
+    E->stats.arena_bytes = hbm_budget_bytes;
+    E->worker = std::thread([E] { E->run(); });
+    *engine = E;
+    return RBSM_OK;
+}
+
+int rbsm_engine_add_light(rbsm_engine *E, const float *shadow_map, int32_t width, int32_t height, int64_t pitch,
+                          int32_t *light_id) {
+    const char *fn = "rbsm_engine_add_light";
+    if (!E || !shadow_map || !light_id) return fail(RBSM_ERR_INVALID_ARG, "%s: null argument", fn);
+    if (width < 1 || height < 1 || width > 65536 || height > 65536 || pitch < width)
+        return fail(RBSM_ERR_INVALID_ARG, "%s: invalid map size or pitch", fn);
+    std::lock_guard<std::mutex> lk(E->mu);
+    MapView mv;
+    mv.t = shadow_map;
+    mv.pitch = pitch;
+    mv.W = width;
+    mv.H = height;
+    E->lights.push_back(mv);
+    *light_id = (int32_t)E->lights.size() - 1;
+    return RBSM_OK;
+}
+
+int rbsm_engine_submit(rbsm_engine *E, const rbsm_request *q, int64_t *ticket) {
+    const char *fn = "rbsm_engine_submit";
+    if (!E || !q || !ticket) return fail(RBSM_ERR_INVALID_ARG, "%s: null argument", fn);
+    if (q->n < 0 || q->n > (int64_t)INT32_MAX) return fail(RBSM_ERR_INVALID_ARG, "%s: n must be in 0..2^31-1", fn);
+    if (q->view_width < 0) return fail(RBSM_ERR_INVALID_ARG, "%s: view_width < 0", fn);
+    if (q->n_lights < 1 || q->n_lights > rbsm::kMaxLights)
+        return fail(RBSM_ERR_INVALID_ARG, "%s: n_lights must be 1..8", fn);
+    const int64_t bytes = request_bytes(*q);
+    if (bytes > E->stats.arena_bytes)
+        return fail(RBSM_ERR_INVALID_ARG, "%s: the request's results exceed the HBM budget", fn);
+    EngineReq *R = new (std::nothrow) EngineReq;
+    if (!R) return fail(RBSM_ERR_INVALID_ARG, "%s: out of host memory", fn);
+    R->req = *q;
+    R->bytes = bytes;
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        for (int l = 0; l < q->n_lights; ++l) {
+            const rbsm_request_light &L = q->lights[l];
+            const char *bad = nullptr;
+            if (L.light < 0 || L.light >= (int32_t)E->lights.size()) bad = "unknown light";
+            else if (L.mode != 0 && L.mode != 1) bad = "mode must be 0 or 1";
+            else if (L.max_dist < 1 || L.max_dist > 64) bad = "max_dist must be in 1..64";
+            else if (L.kernel_radius < 0 || L.kernel_radius > 32) bad = "kernel_radius must be in 0..32";
+            else if (L.mode == 0 && L.kernel_radius != 0) bad = "kernel_radius must be 0 in hard mode";
+            else if (q->n > 0 && !L.frags) bad = "null fragments";
+            if (bad) {
+                delete R;
+                return fail(RBSM_ERR_INVALID_ARG, "rbsm_engine_submit: %s", bad);
+            }
+            R->maps[l] = E->lights[L.light];
+        }
+        if (!E->error.empty()) {
+            delete R;
+            return fail(RBSM_ERR_HIP, "rbsm_engine_submit: engine failed earlier: %s", E->error.c_str());
+        }
+    }
+    if (hipEventCreateWithFlags(&R->done, hipEventDisableTiming) != hipSuccess) {
+        delete R;
+        return fail(RBSM_ERR_HIP, "%s: could not create an event", fn);
+    }
+    std::lock_guard<std::mutex> lk(E->mu);
+    R->t_submit = Clock::now();
+    R->ticket = E->next_ticket++;
+    E->tickets[R->ticket] = R;
+    E->queue.push_back(R);
+    E->stats.submitted += 1;
+    E->stats.queued += 1;
+    *ticket = R->ticket;
+    E->cv_work.notify_one();
+    return RBSM_OK;
+}
+
+int rbsm_engine_wait(rbsm_engine *E, int64_t ticket, int32_t timeout_ms, double *latency_ms) {
+    const char *fn = "rbsm_engine_wait";
+    if (!E) return fail(RBSM_ERR_INVALID_ARG, "%s: engine is null", fn);
+    std::unique_lock<std::mutex> lk(E->mu);
+    auto it = E->tickets.find(ticket);
+    if (it == E->tickets.end()) return fail(RBSM_ERR_INVALID_ARG, "%s: unknown ticket", fn);
+    EngineReq *R = it->second;
+    auto ready = [&] { return R->status != 0; };
+    if (timeout_ms < 0) E->cv_done.wait(lk, ready);
+    else if (!E->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) return 0;
+    const int status = R->status;
+    const double ms = std::chrono::duration<double, std::milli>(R->t_done - R->t_submit).count();
+    E->tickets.erase(it);
+    const std::string err = E->error;
+    lk.unlock();
+    (void)hipEventDestroy(R->done);
+    delete R;
+    if (status < 0) return fail(RBSM_ERR_HIP, "rbsm_engine_wait: %s", err.c_str());
+    if (latency_ms) *latency_ms = ms;
+    return 1;
+}
+
+int rbsm_engine_get_stats(rbsm_engine *E, rbsm_engine_stats *stats) {
+    if (!E || !stats) return fail(RBSM_ERR_INVALID_ARG, "rbsm_engine_get_stats: null argument");
+    std::lock_guard<std::mutex> lk(E->mu);
+    *stats = E->stats;
+    return RBSM_OK;
+}
+
+void rbsm_engine_destroy(rbsm_engine *E) {
+    if (!E) return;
+    if (E->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(E->mu);
+            E->stop = true;
+        }
+        E->cv_work.notify_all();
+        E->worker.join();
+    }
+    if (E->s_compute) (void)hipStreamSynchronize(E->s_compute);
+    if (E->s_copy) (void)hipStreamSynchronize(E->s_copy);
+    for (auto &kv : E->tickets) {
+        (void)hipEventDestroy(kv.second->done);
+        delete kv.second;
+    }
+    for (Slot &S : E->slots) {
+        if (S.d_jobs) (void)hipFree(S.d_jobs);
+        if (S.d_comp) (void)hipFree(S.d_comp);
+        if (S.h_jobs) (void)hipHostFree(S.h_jobs);
+        if (S.h_comp) (void)hipHostFree(S.h_comp);
+        if (S.compute_done) (void)hipEventDestroy(S.compute_done);
+    }
+    if (E->s_compute) (void)hipStreamDestroy(E->s_compute);
+    if (E->s_copy) (void)hipStreamDestroy(E->s_copy);
+    if (E->d_arena) (void)hipFree(E->d_arena);
+    delete E;
+}
+
 const char *rbsm_last_error(void) { return g_err; }
 
-int32_t rbsm_abi_version(void) { return 100; }
+int32_t rbsm_abi_version(void) { return 101; }
 
 }  // extern "C"

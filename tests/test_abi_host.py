@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.rbsm_abi_version() == 100
+    assert lib.rbsm_abi_version() == 101
 
 
 def _p(**kw):
@@ -117,3 +117,35 @@ def test_plan_rejects_bad_jobs_on_host(lib):
     assert lib.rbsm_plan_create(jobs, 0, None, ctypes.byref(h)) == -1
     assert lib.rbsm_plan_launch(None, None) == -1
     assert lib.rbsm_plan_fragments(None) == -1
+
+
+def test_composite_validated_on_host(lib):
+    vp = ctypes.c_void_p
+    ptrs = (vp * 2)(0x100000, 0x200000)
+    modes = (ctypes.c_int32 * 2)(0, 1)
+    w = (ctypes.c_float * 2)(0.5, 0.5)
+    assert lib.rbsm_composite(16, 0, ptrs, modes, w, 0x300000, None) == -1      # no lights
+    assert lib.rbsm_composite(16, 9, ptrs, modes, w, 0x300000, None) == -1      # too many
+    assert lib.rbsm_composite(-1, 2, ptrs, modes, w, 0x300000, None) == -1
+    assert lib.rbsm_composite(16, 2, None, modes, w, 0x300000, None) == -1
+    bad = (ctypes.c_int32 * 2)(0, 3)
+    assert lib.rbsm_composite(16, 2, ptrs, bad, w, 0x300000, None) == -1
+    assert lib.rbsm_composite(16, 2, ptrs, modes, w, 0x200008, None) == -1      # out overlaps an input
+    assert "overlap" in lib.rbsm_last_error().decode()
+    assert lib.rbsm_composite(0, 2, ptrs, modes, w, 0, None) == 0               # empty is a no-op
+
+
+def test_engine_arguments_validated_on_host(lib):
+    import paper_1711_07793_amd as rb
+    h = ctypes.c_void_p()
+    assert lib.rbsm_engine_create(100, 4, ctypes.byref(h)) == -1 and not h.value   # budget too small
+    assert lib.rbsm_engine_create(1 << 20, 0, ctypes.byref(h)) == -1
+    assert lib.rbsm_engine_create(1 << 20, 4, None) == -1
+    t = ctypes.c_int64()
+    q = rb.RbsmRequest()
+    assert lib.rbsm_engine_submit(None, ctypes.byref(q), ctypes.byref(t)) == -1
+    lid = ctypes.c_int32()
+    assert lib.rbsm_engine_add_light(None, 0x1000, 4, 4, 4, ctypes.byref(lid)) == -1
+    assert lib.rbsm_engine_wait(None, 1, 0, None) == -1
+    assert lib.rbsm_engine_get_stats(None, None) == -1
+    lib.rbsm_engine_destroy(None)

@@ -1,0 +1,218 @@
+"""Serving form and multi-light compositing on the GPU.
+
+Every per-light result of the engine must be bitwise the plain entry point's,
+every composite bitwise the composite entry point's on those results, and all
+of it must be the same whether a request runs alone or mixed with others under
+a tight HBM budget.  A sample is checked against the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SOFT_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rb():
+    import paper_1711_07793_amd as rb
+    rb.load_library()
+    return rb
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def world(rb):
+    """6 resident lights (random-triangle maps 128^2..512^2) and, for each
+    light, camera fragments of 3 small views (device-resident)."""
+    sizes = [128, 256, 512, 128, 256, 512]
+    views = [(160, 90), (240, 135), (320, 180)]
+    lights, frags = [], {}
+    for li, S in enumerate(sizes):
+        sc = synth.triangle_scene(7100 + li, S, S, 48, fence=(li % 3 == 2))
+        m = sc.raster()
+        lights.append(m)
+        for vi, (w, h) in enumerate(views):
+            frags[(li, vi)] = sc.camera_fragments(7200 + 10 * li + vi, w, h)
+    dev_maps = [torch.from_numpy(m).cuda() for m in lights]
+    dev_frags = {k: torch.from_numpy(v).cuda() for k, v in frags.items()}
+    rng = np.random.default_rng(7300)
+    reqs = []
+    for q in range(24):
+        vi = int(rng.integers(0, 3))
+        nl = int(rng.integers(1, 5))
+        ls = rng.choice(6, size=nl, replace=False)
+        L = []
+        for li in ls:
+            mode = int(li % 2)
+            radius = 2 if (mode == 1 and q % 5 == 0) else 0
+            L.append(dict(light=int(li), mode=mode, depth_bias=1e-4, max_dist=16 if li < 3 else 24,
+                          kernel_radius=radius, weight=float(np.float32(rng.uniform(0.1, 1.0)))))
+        reqs.append(dict(view=vi, lights=L))
+    return dict(maps=lights, dev_maps=dev_maps, frags=frags, dev_frags=dev_frags, views=views, reqs=reqs)
+
+
+def _outs(world, req, pinned=True):
+    w, h = world["views"][req["view"]]
+    n = w * h
+    outs = [torch.empty(n, dtype=torch.uint8 if L["mode"] == 0 else torch.float32).pin_memory() if pinned
+            else torch.empty(n, dtype=torch.uint8 if L["mode"] == 0 else torch.float32) for L in req["lights"]]
+    comp = torch.empty(n, dtype=torch.float32).pin_memory() if pinned else torch.empty(n, dtype=torch.float32)
+    return n, w, outs, comp
+
+
+def _submit(eng, ids, world, req, outs, comp):
+    w, h = world["views"][req["view"]]
+    lights = []
+    for L, o in zip(req["lights"], outs):
+        lights.append(dict(L, light=ids[L["light"]], frags=world["dev_frags"][(L["light"], req["view"])], out=o))
+    return eng.submit(w * h, lights, view_width=w, composite=comp)
+
+
+def _run(rb, world, budget, max_inflight, burst):
+    eng = rb.Engine(budget, max_inflight)
+    ids = [eng.add_light(m) for m in world["dev_maps"]]
+    results = []
+    tickets = []
+    for req in world["reqs"]:
+        n, w, outs, comp = _outs(world, req)
+        t = _submit(eng, ids, world, req, outs, comp)
+        if burst:
+            tickets.append(t)
+        else:
+            assert eng.wait(t, 60000) is not None
+        results.append((outs, comp))
+    for t in tickets:
+        assert eng.wait(t, 60000) is not None
+    st = eng.stats()
+    eng.close()
+    return [([o.numpy().copy() for o in outs], comp.numpy().copy()) for outs, comp in results], st
+
+
+def _plain(rb, world, req):
+    w, h = world["views"][req["view"]]
+    outs = []
+    for L in req["lights"]:
+        m = world["dev_maps"][L["light"]]
+        f = world["dev_frags"][(L["light"], req["view"])]
+        p = dict(width=m.shape[1], height=m.shape[0], depth_bias=L["depth_bias"], max_dist=L["max_dist"],
+                 kernel_radius=L["kernel_radius"], view_width=w)
+        outs.append(rb.rbsm_visibility(m, f, p) if L["mode"] == 0 else rb.rsmss_visibility(m, f, p))
+    comp = rb.rbsm_composite(outs, [L["mode"] for L in req["lights"]], [L["weight"] for L in req["lights"]])
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs], comp.cpu().numpy()
+
+
+def test_composite_entry_point_matches_oracle(rb):
+    n = 100003
+    a = synth.uniform_floats(41, n)
+    b = synth.uniform_floats(42, n)
+    h = (synth.uniform_floats(43, n) < 0.5).astype(np.uint8)
+    w = [0.7, 0.2, 0.1]
+    want = oracle.composite([a, h, b], w)
+    got = rb.rbsm_composite([torch.from_numpy(a).cuda(), torch.from_numpy(h).cuda(), torch.from_numpy(b).cuda()],
+                            [1, 0, 1], w).cpu().numpy()
+    assert np.array_equal(got, want)
+    one = rb.rbsm_composite([torch.from_numpy(h).cuda()], [0], [1.0]).cpu().numpy()
+    assert np.array_equal(one, h.astype(np.float32))
+
+
+def test_alone_and_in_the_mix_are_identical(rb, world):
+    say("serving: alone")
+    alone, st_a = _run(rb, world, budget=256 << 20, max_inflight=8, burst=False)
+    # a budget that holds only a few requests' results at a time forces
+    # admission waits, several requests per step and overlapping steps
+    say("serving: mix")
+    mix, st_m = _run(rb, world, budget=2 << 20, max_inflight=6, burst=True)
+    assert st_a["completed"] == st_m["completed"] == len(world["reqs"])
+    assert st_m["launches"] < len(world["reqs"])          # requests were batched together
+    assert st_m["arena_peak_bytes"] <= st_m["arena_bytes"]
+    for k, ((oa, ca), (om, cm)) in enumerate(zip(alone, mix)):
+        for x, y in zip(oa, om):
+            assert np.array_equal(x, y), k
+        assert np.array_equal(ca, cm), k
+    say("serving: plain entry points")
+    for k, req in enumerate(world["reqs"]):
+        po, pc = _plain(rb, world, req)
+        for x, y in zip(alone[k][0], po):
+            assert np.array_equal(x, y), k
+        assert np.array_equal(alone[k][1], pc), k
+
+
+def test_engine_results_against_oracle(rb, world):
+    eng = rb.Engine(64 << 20, 4)
+    ids = [eng.add_light(m) for m in world["dev_maps"]]
+    for req in world["reqs"][:6]:
+        n, w, outs, comp = _outs(world, req)
+        t = _submit(eng, ids, world, req, outs, comp)
+        assert eng.wait(t, 60000) is not None
+        want = []
+        for L, o in zip(req["lights"], outs):
+            m = world["maps"][L["light"]]
+            f = world["frags"][(L["light"], req["view"])]
+            p = dict(width=m.shape[1], height=m.shape[0], pitch=m.shape[1], depth_bias=L["depth_bias"],
+                     max_dist=L["max_dist"], kernel_radius=L["kernel_radius"])
+            if L["mode"] == 0:
+                v = oracle.rbsm_hard(m, f, p)
+                assert np.array_equal(o.numpy(), v)
+            else:
+                v = oracle.rsmss(m, f, p)
+                assert np.max(np.abs(o.numpy().astype(np.float64) - v)) <= SOFT_TOL
+            want.append(v)
+        wc = oracle.composite(want, [L["weight"] for L in req["lights"]])
+        tol = SOFT_TOL * sum(abs(L["weight"]) for L in req["lights"]) + 1e-6
+        assert np.max(np.abs(comp.numpy().astype(np.float64) - wc)) <= tol
+    eng.close()
+
+
+def test_engine_rejections_and_empty_request(rb, world):
+    eng = rb.Engine(1 << 20, 2)
+    lid = eng.add_light(world["dev_maps"][0])
+    f = world["dev_frags"][(0, 2)]
+    n = f.numel() // 3
+    with pytest.raises(rb.RbsmError):   # results alone exceed the budget
+        eng.submit(n, [dict(light=lid, mode=1, frags=f)] * 8)
+    with pytest.raises(rb.RbsmError):   # unknown light
+        eng.submit(n, [dict(light=99, mode=0, frags=f)])
+    with pytest.raises(rb.RbsmError):   # radius in hard mode
+        eng.submit(n, [dict(light=lid, mode=0, frags=f, kernel_radius=2)])
+    with pytest.raises(rb.RbsmError):
+        eng.wait(12345, 10)
+    empty = torch.empty(0, 3, dtype=torch.float32, device="cuda")
+    t = eng.submit(0, [dict(light=lid, mode=0, frags=empty)])
+    assert eng.wait(t, 10000) is not None
+    eng.close()
+
+
+def test_poisson_arrivals_complete(rb, world):
+    """Requests arriving while others run: all complete, latencies positive."""
+    import threading
+    import time
+    eng = rb.Engine(8 << 20, 16)
+    ids = [eng.add_light(m) for m in world["dev_maps"]]
+    rng = np.random.default_rng(7400)
+    gaps = rng.exponential(0.0005, size=len(world["reqs"]))
+    tickets, bufs = [], []
+
+    def producer():
+        for req, g in zip(world["reqs"], gaps):
+            time.sleep(g)
+            n, w, outs, comp = _outs(world, req)
+            bufs.append((outs, comp))
+            tickets.append(_submit(eng, ids, world, req, outs, comp))
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    lat = [eng.wait(t, 60000) for t in tickets]
+    assert all(x is not None and x > 0 for x in lat)
+    st = eng.stats()
+    assert st["completed"] == len(world["reqs"]) and st["queued"] == 0 and st["inflight"] == 0
+    eng.close()

@@ -476,3 +476,30 @@ def test_read_counts():
     # shadowed fragment in hard mode: only the centre
     touch, reads = oracle.touched_texels(m, np.array([[0.05, 0.05, 0.9]], np.float32), p, hard=True)
     assert reads == 1 and touch.sum() == 1
+
+
+# --------------------------------------------------------------------------
+# Multi-light compositing (serving extension)
+# --------------------------------------------------------------------------
+
+def test_composite_worked_examples():
+    rows = [list(map(float, ln.split())) for ln in open(os.path.join(GOLDEN, "composite_examples.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for r in rows:
+        m = np.array([int(r[0])], np.uint8)
+        a, b = np.array([r[1]], np.float32), np.array([r[2]], np.float32)
+        got = oracle.composite([m, a, b], r[3:6])
+        assert got[0] == np.float32(r[6]), r
+
+
+def test_composite_identities():
+    rng = np.random.default_rng(21)
+    v = rng.random(1000).astype(np.float32)
+    h = (rng.random(1000) < 0.5).astype(np.uint8)
+    assert np.array_equal(oracle.composite([v], [1.0]), v)          # one light, weight 1
+    assert np.array_equal(oracle.composite([h], [1.0]), h.astype(np.float32))
+    assert np.array_equal(oracle.composite([v, h], [0.0, 0.0]), np.zeros(1000, np.float32))
+    # power-of-two weights scale exactly; order of lights matters only through rounding
+    assert np.array_equal(oracle.composite([v], [0.25]), v * np.float32(0.25))
+    both = oracle.composite([v, h], [0.5, 0.5])
+    assert np.max(np.abs(both.astype(np.float64) - 0.5 * (v + h))) <= 2 ** -24
