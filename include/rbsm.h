@@ -218,14 +218,17 @@ int rbsm_composite(int64_t n, int32_t n_lights, const void *const *vis, const in
  * (the only device allocation it makes), two streams and a scheduler thread.
  * A request is one view: its light-space fragments for 1..8 registered
  * lights (device memory, owned by the caller and left untouched until the
- * request completes), plus host buffers for the results.  The engine admits
- * requests first come, first served while their result buffers fit in the
- * arena and fewer than max_inflight requests are admitted; each scheduling
- * step runs one batched pass over the jobs of every admitted request (each
- * per-light result is bitwise the plain entry point's), the RPCF jobs, and
- * one compositing launch, then copies results to the host buffers on a second
- * stream while the next step computes.  Requests that arrive while others run
- * join the next step.  Results are the same alone and in any mix.
+ * request completes), plus buffers for the results.  A result buffer in
+ * device memory of the engine's device is written in place by the kernels;
+ * any other (host) buffer is staged in the arena and copied back.  The engine
+ * admits requests first come, first served while their staged buffers (and
+ * the per-light results a composite needs) fit in the arena and fewer than
+ * max_inflight requests are admitted; each scheduling step runs one batched
+ * pass over the jobs of every admitted request (each per-light result is
+ * bitwise the plain entry point's), the RPCF jobs, and one compositing
+ * launch, then copies staged results back on a second stream while the next
+ * step computes.  Requests that arrive while others run join the next step.
+ * Results are the same alone and in any mix.
  */
 typedef struct rbsm_engine rbsm_engine;  /* opaque */
 
@@ -237,8 +240,10 @@ typedef struct {
     int32_t max_dist;      /* 1..64 */
     int32_t kernel_radius; /* mode 1 only, 0..32 */
     float weight;          /* this light's weight in the composite */
-    void *out_host;        /* host uint8_t[n] (mode 0) or float[n] (mode 1) for this
-                              light's result, or NULL; pinned memory overlaps best */
+    void *out;             /* uint8_t[n] (mode 0) or float[n] (mode 1) for this light's
+                              result, or NULL; device memory (written in place, must
+                              not overlap any input) or host memory (pinned overlaps
+                              best) */
 } rbsm_request_light;
 
 typedef struct {
@@ -246,7 +251,7 @@ typedef struct {
     int32_t view_width;    /* layout hint as in rbsm_params */
     int32_t n_lights;      /* 1..8 */
     rbsm_request_light lights[8];
-    float *composite_host; /* host float[n] for the composite, or NULL */
+    float *composite;      /* float[n] for the composite, or NULL; device or host as `out` */
 } rbsm_request;
 
 typedef struct {
@@ -254,6 +259,7 @@ typedef struct {
     int64_t launches, jobs_launched;  /* scheduling steps, (request, light) jobs */
     int64_t fragments_completed;      /* sum over completed requests of n * n_lights */
     int64_t arena_bytes, arena_peak_bytes;
+    int64_t gpu_busy_ns;              /* summed GPU time of the scheduling steps' compute */
 } rbsm_engine_stats;
 
 /* Create an engine on the current device.  hbm_budget_bytes >= 4096,
@@ -266,11 +272,12 @@ int rbsm_engine_add_light(rbsm_engine *engine, const float *shadow_map, int32_t 
                           int32_t *light_id);
 
 /* Queue a request (copied; the arrays it points to are not).  Rejected when
- * its result buffers alone exceed the budget.  Writes a ticket. */
+ * its staged buffers alone exceed the budget, or a device result buffer
+ * overlaps an input.  Writes a ticket. */
 int rbsm_engine_submit(rbsm_engine *engine, const rbsm_request *request, int64_t *ticket);
 
-/* Wait up to timeout_ms (< 0: forever) for a ticket.  Returns 1 when its
- * results are in the host buffers (the ticket is then forgotten and
+/* Wait up to timeout_ms (< 0: forever) for a ticket.  Returns 1 when all its
+ * results are in their buffers (the ticket is then forgotten and
  * *latency_ms, if non-NULL, is submit-to-completion time), 0 on time-out, a
  * negative code on failure. */
 int rbsm_engine_wait(rbsm_engine *engine, int64_t ticket, int32_t timeout_ms, double *latency_ms);

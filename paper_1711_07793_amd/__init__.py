@@ -60,20 +60,20 @@ class RbsmRequestLight(ctypes.Structure):
     """Mirror of ``rbsm_request_light``."""
     _fields_ = [("light", ctypes.c_int32), ("mode", ctypes.c_int32), ("frags", ctypes.c_void_p),
                 ("depth_bias", ctypes.c_float), ("max_dist", ctypes.c_int32), ("kernel_radius", ctypes.c_int32),
-                ("weight", ctypes.c_float), ("out_host", ctypes.c_void_p)]
+                ("weight", ctypes.c_float), ("out", ctypes.c_void_p)]
 
 
 class RbsmRequest(ctypes.Structure):
     """Mirror of ``rbsm_request``."""
     _fields_ = [("n", ctypes.c_int64), ("view_width", ctypes.c_int32), ("n_lights", ctypes.c_int32),
-                ("lights", RbsmRequestLight * 8), ("composite_host", ctypes.c_void_p)]
+                ("lights", RbsmRequestLight * 8), ("composite", ctypes.c_void_p)]
 
 
 class RbsmEngineStats(ctypes.Structure):
     """Mirror of ``rbsm_engine_stats``."""
     _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "queued", "inflight", "launches",
                                               "jobs_launched", "fragments_completed", "arena_bytes",
-                                              "arena_peak_bytes")]
+                                              "arena_peak_bytes", "gpu_busy_ns")]
 
 
 class RbsmError(RuntimeError):
@@ -360,10 +360,11 @@ class Engine:
 
     ``submit`` takes one view: ``n`` fragments, a layout hint and 1..8
     lights, each ``dict(light=id, mode=0|1, frags=<device float32 [n, 3]>,
-    depth_bias=, max_dist=, kernel_radius=, weight=, out=<host tensor or
-    None>)``, plus an optional host float32 ``composite`` tensor.  Host
-    tensors should be pinned.  The tensors are kept alive until ``wait``
-    returns for that ticket.
+    depth_bias=, max_dist=, kernel_radius=, weight=, out=<tensor or None>)``,
+    plus an optional float32 ``composite`` tensor.  Result tensors on the GPU
+    are written in place; host tensors (pinned, for overlap) are staged in the
+    engine's budget and copied back.  The tensors are kept alive until
+    ``wait`` returns for that ticket.
     """
 
     def __init__(self, hbm_budget_bytes: int, max_inflight: int = 64):
@@ -388,6 +389,22 @@ class Engine:
         return int(lid.value)
 
     def submit(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None) -> int:
+        q, keep = self.build_request(n, lights, view_width, composite)
+        return self.submit_built(q, keep)
+
+    def submit_built(self, q: "RbsmRequest", keep=None) -> int:
+        """Submit a request built by ``build_request`` (marshalling done ahead
+        of time)."""
+        t = ctypes.c_int64()
+        st = self._lib.rbsm_engine_submit(self._h, ctypes.byref(q), ctypes.byref(t))
+        if st != RBSM_OK:
+            raise RbsmError(rbsm_last_error())
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def build_request(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None):
+        """Marshal one request into an ``RbsmRequest``; returns it with the
+        tensors that must stay alive until it completes."""
         if not 1 <= len(lights) <= 8:
             raise RbsmError("submit: need 1..8 lights")
         q = RbsmRequest()
@@ -400,23 +417,18 @@ class Engine:
             out = L.get("out")
             if out is not None:
                 want = torch.uint8 if L.get("mode", 0) == 0 else torch.float32
-                if out.device.type != "cpu" or out.dtype != want or out.numel() != n or not out.is_contiguous():
-                    raise RbsmError("submit: out must be a contiguous host tensor of n results of the mode's type")
+                if out.dtype != want or out.numel() != n or not out.is_contiguous():
+                    raise RbsmError("submit: out must be a contiguous tensor of n results of the mode's type")
             q.lights[i] = RbsmRequestLight(int(L["light"]), int(L.get("mode", 0)), f.data_ptr(),
                                            float(L.get("depth_bias", 0.0)), int(L.get("max_dist", 16)),
                                            int(L.get("kernel_radius", 0)), float(L.get("weight", 1.0)),
                                            out.data_ptr() if out is not None else None)
             keep += [f, out]
         if composite is not None:
-            if composite.device.type != "cpu" or composite.dtype != torch.float32 or composite.numel() != n:
-                raise RbsmError("submit: composite must be a host float32 tensor of n values")
-            q.composite_host = composite.data_ptr()
-        t = ctypes.c_int64()
-        st = self._lib.rbsm_engine_submit(self._h, ctypes.byref(q), ctypes.byref(t))
-        if st != RBSM_OK:
-            raise RbsmError(rbsm_last_error())
-        self._keep[int(t.value)] = keep
-        return int(t.value)
+            if composite.dtype != torch.float32 or composite.numel() != n or not composite.is_contiguous():
+                raise RbsmError("submit: composite must be a contiguous float32 tensor of n values")
+            q.composite = composite.data_ptr()
+        return q, keep
 
     def wait(self, ticket: int, timeout_ms: int = -1):
         """Latency in ms (submit to results on the host), or None on time-out."""

@@ -535,16 +535,12 @@ int rbsm_engine_create(int64_t hbm_budget_bytes, int32_t max_inflight, rbsm_engi
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->s_copy, hipStreamNonBlocking);
     for (int s = 0; s < rbsm::kServeSlots && e == hipSuccess; ++s) {
         Slot &S = E->slots[s];
-        e = hipMalloc(&S.d_jobs, sizeof(JobDev) * rbsm::kServeMaxJobs);
-        if (e == hipSuccess) e = hipMalloc(&S.d_comp, sizeof(rbsm::CompJob) * rbsm::kServeMaxReqs);
-        if (e == hipSuccess) e = hipHostMalloc(&S.h_jobs, sizeof(JobDev) * rbsm::kServeMaxJobs, hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc(&S.h_comp, sizeof(rbsm::CompJob) * rbsm::kServeMaxReqs, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&S.compute_done, hipEventDisableTiming);
+        e = hipEventCreate(&S.compute_start);
+        if (e == hipSuccess) e = hipEventCreate(&S.compute_done);
     }
     if (e != hipSuccess) {
         rbsm_engine_destroy(E);
-        return fail(RBSM_ERR_HIP, "%s: could not allocate the arena, streams or tables", fn);
+        return fail(RBSM_ERR_HIP, "%s: could not allocate the arena, streams or events", fn);
     }
     E->arena.reset(hbm_budget_bytes);
     E->stats.arena_bytes = hbm_budget_bytes;
@@ -577,13 +573,16 @@ int rbsm_engine_submit(rbsm_engine *E, const rbsm_request *q, int64_t *ticket) {
     if (q->view_width < 0) return fail(RBSM_ERR_INVALID_ARG, "%s: view_width < 0", fn);
     if (q->n_lights < 1 || q->n_lights > rbsm::kMaxLights)
         return fail(RBSM_ERR_INVALID_ARG, "%s: n_lights must be 1..8", fn);
-    const int64_t bytes = request_bytes(*q);
-    if (bytes > E->stats.arena_bytes)
-        return fail(RBSM_ERR_INVALID_ARG, "%s: the request's results exceed the HBM budget", fn);
     EngineReq *R = new (std::nothrow) EngineReq;
     if (!R) return fail(RBSM_ERR_INVALID_ARG, "%s: out of host memory", fn);
     R->req = *q;
-    R->bytes = bytes;
+    for (int l = 0; l < q->n_lights; ++l) R->direct_out[l] = q->n > 0 && is_device_memory(q->lights[l].out, E->device);
+    R->direct_comp = q->n > 0 && is_device_memory(q->composite, E->device);
+    R->bytes = request_bytes(*R);
+    if (R->bytes > E->stats.arena_bytes) {
+        delete R;
+        return fail(RBSM_ERR_INVALID_ARG, "%s: the request's staged results exceed the HBM budget", fn);
+    }
     {
         std::lock_guard<std::mutex> lk(E->mu);
         for (int l = 0; l < q->n_lights; ++l) {
@@ -600,6 +599,27 @@ int rbsm_engine_submit(rbsm_engine *E, const rbsm_request *q, int64_t *ticket) {
                 return fail(RBSM_ERR_INVALID_ARG, "rbsm_engine_submit: %s", bad);
             }
             R->maps[l] = E->lights[L.light];
+        }
+        // results written in place must not overlap any input of the request
+        for (int a = 0; a < q->n_lights + 1; ++a) {
+            const bool is_comp = a == q->n_lights;
+            if (is_comp ? !R->direct_comp : !R->direct_out[a]) continue;
+            const void *dst = is_comp ? (const void *)q->composite : q->lights[a].out;
+            const size_t db = (size_t)q->n * (is_comp || q->lights[a].mode != 0 ? 4u : 1u);
+            for (int b = 0; b < q->n_lights; ++b) {
+                const MapView &mv = R->maps[b];
+                const size_t mb = ((size_t)(mv.H - 1) * (size_t)mv.pitch + (size_t)mv.W) * 4u;
+                bool bad = overlaps(dst, db, q->lights[b].frags, (size_t)q->n * 12u) || overlaps(dst, db, mv.t, mb);
+                if (!is_comp && b != a && R->direct_out[b])
+                    bad = bad || overlaps(dst, db, q->lights[b].out, (size_t)q->n * (q->lights[b].mode == 0 ? 1u : 4u));
+                if (is_comp && R->direct_out[b])
+                    bad = bad || overlaps(dst, db, q->lights[b].out, (size_t)q->n * (q->lights[b].mode == 0 ? 1u : 4u));
+                if (bad) {
+                    delete R;
+                    return fail(RBSM_ERR_INVALID_ARG, "rbsm_engine_submit: a device result buffer overlaps an input",
+                                nullptr);
+                }
+            }
         }
         if (!E->error.empty()) {
             delete R;
@@ -668,10 +688,7 @@ void rbsm_engine_destroy(rbsm_engine *E) {
         delete kv.second;
     }
     for (Slot &S : E->slots) {
-        if (S.d_jobs) (void)hipFree(S.d_jobs);
-        if (S.d_comp) (void)hipFree(S.d_comp);
-        if (S.h_jobs) (void)hipHostFree(S.h_jobs);
-        if (S.h_comp) (void)hipHostFree(S.h_comp);
+        if (S.compute_start) (void)hipEventDestroy(S.compute_start);
         if (S.compute_done) (void)hipEventDestroy(S.compute_done);
     }
     if (E->s_compute) (void)hipStreamDestroy(E->s_compute);

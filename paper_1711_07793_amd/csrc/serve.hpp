@@ -13,9 +13,10 @@
 // in-flight slot are free; every scheduling step launches ONE pass over the
 // jobs of all admitted requests (the same tile code as the plain entry points,
 // so each per-light result is bitwise that of rbsm_visibility /
-// rsmss_visibility), then RPCF jobs, then one compositing launch, and copies
-// results to the callers' host buffers on a second stream while the next step
-// computes.  Requests that arrive while others run join the next step.
+// rsmss_visibility), then RPCF jobs, then one compositing launch.  Result
+// buffers in device memory are written in place; host buffers are staged in
+// the arena and copied back on a second stream while the next step computes.
+// Requests that arrive while others run join the next step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,10 +38,11 @@
 namespace rbsm {
 
 constexpr int kMaxLights = 8;
-constexpr int kServeMaxJobs = 256;   // jobs per scheduling step
+constexpr int kServeMaxJobs = 256;   // (request, light) jobs per scheduling step
 constexpr int kServeMaxReqs = 64;    // requests per scheduling step
-constexpr int kServeSlots = 4;       // table slots (steps whose compute may be pending)
-constexpr int kServeComputeAhead = 2;
+constexpr int kServeSlots = 2;       // steps whose compute may be pending
+constexpr int kArgJobs = 40;         // tile jobs per launch, passed in the kernel arguments
+constexpr int kArgComp = 20;         // composites per launch, passed in the kernel arguments
 
 // One view's composite: out[k] = sum_l w[l] * vis_l[k].
 struct CompJob {
@@ -50,7 +52,6 @@ struct CompJob {
     int32_t n_lights;
     int64_t n;
     float *out;
-    int64_t block_base;  // first block of this job in a batched launch
 };
 
 constexpr int kCompT = 256, kCompF = 4;  // threads, fragments per thread
@@ -73,49 +74,50 @@ __global__ __launch_bounds__(kCompT) void composite_kernel(CompJob J) {
     composite_range(J, (int64_t)blockIdx.x * (kCompT * kCompF) + threadIdx.x);
 }
 
-// Several composites in one launch; jobs sorted by block_base.
-__global__ __launch_bounds__(kCompT) void composite_batch_kernel(const CompJob *__restrict__ jobs, int n_jobs) {
-    __shared__ int64_t s_base[kServeMaxReqs];
-    for (int t = threadIdx.x; t < n_jobs; t += kCompT) s_base[t] = jobs[t].block_base;
-    __syncthreads();
-    const int64_t g = blockIdx.x;
-    int lo = 0, hi = n_jobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_base[mid] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    const CompJob J = jobs[lo];
-    composite_range(J, (g - J.block_base) * (kCompT * kCompF) + threadIdx.x);
-}
-
 inline int64_t composite_blocks(int64_t n) { return (n + kCompT * kCompF - 1) / (kCompT * kCompF); }
 
-// The batched tile pass of a scheduling step: like batch_kernel, but the
-// block -> job lookup is a binary search over the jobs' first tiles (staged
-// in LDS), so a step needs no per-tile table.
-template <int TW>
-__global__ __launch_bounds__(kT) void serve_kernel(const JobDev *__restrict__ jobs, int n_jobs, int apron, int cap) {
-    extern __shared__ float s_tex[];
-    __shared__ TileShared sh;
-    __shared__ int64_t s_base[kServeMaxJobs];
-    for (int t = threadIdx.x; t < n_jobs; t += kT) s_base[t] = jobs[t].tile_base;
-    __syncthreads();
-    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
-    int lo = 0, hi = n_jobs - 1;
+// Job tables of one launch travel in the kernel arguments (read with scalar
+// loads, no copy of their own); a block finds its job by binary search over
+// the jobs' first blocks.
+struct CompArgs {
+    int32_t n_jobs;
+    int64_t first[kArgComp];
+    CompJob jobs[kArgComp];
+};
+
+struct ServeArgs {
+    int32_t n_jobs;
+    int64_t first[kArgJobs];
+    JobDev jobs[kArgJobs];
+};
+
+__device__ __forceinline__ int find_job(const int64_t *first, int n, int64_t g) {
+    int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_base[mid] <= g) lo = mid;
+        if (first[mid] <= g) lo = mid;
         else hi = mid - 1;
     }
-    const JobDev J = jobs[lo];
-    const int64_t tile = g - J.tile_base;
-    if (J.mode == 0)
-        process_tile<true, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                               tile, sh, s_tex);
-    else
-        process_tile<false, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                                tile, sh, s_tex);
+    return lo;
+}
+
+__global__ __launch_bounds__(kCompT) void composite_batch_kernel(const CompArgs a) {
+    const int64_t g = blockIdx.x;
+    const int j = find_job(a.first, a.n_jobs, g);
+    composite_range(a.jobs[j], (g - a.first[j]) * (kCompT * kCompF) + threadIdx.x);
+}
+
+// The batched tile pass of a scheduling step, one launch per mode and chunk of
+// jobs: each tile runs the code of the single-view pass.
+template <bool HARD, int TW>
+__global__ __launch_bounds__(kT) void serve_kernel(const ServeArgs a, int apron, int cap) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
+    const int j = find_job(a.first, a.n_jobs, g);
+    const JobDev &J = a.jobs[j];
+    process_tile<HARD, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
+                           g - a.first[j], sh, s_tex);
 }
 
 }  // namespace rbsm
@@ -133,25 +135,40 @@ struct EngineReq {
     rbsm_request req{};
     MapView maps[rbsm::kMaxLights]{};
     int64_t off = -1, bytes = 0;         // arena block
-    void *d_out[rbsm::kMaxLights]{};     // per-light device results (in the arena)
-    float *d_comp = nullptr;             // device composite (in the arena), or null
+    void *d_out[rbsm::kMaxLights]{};     // per-light device results (caller's or arena)
+    float *d_comp = nullptr;             // device composite (caller's or arena), or null
+    bool direct_out[rbsm::kMaxLights]{}; // the caller's buffer is device memory: written in place
+    bool direct_comp = false;
     Clock::time_point t_submit, t_done;
-    hipEvent_t done = nullptr;           // results are in the host buffers
+    hipEvent_t done = nullptr;           // every result is in its buffer
     int status = 0;                      // 0 pending, 1 done, < 0 failed
 };
 
 struct Slot {
-    JobDev *d_jobs = nullptr, *h_jobs = nullptr;
-    rbsm::CompJob *d_comp = nullptr, *h_comp = nullptr;
-    hipEvent_t compute_done = nullptr;
+    hipEvent_t compute_start = nullptr, compute_done = nullptr;  // timing events around a step's compute
     bool busy = false;
 };
 
-int64_t request_bytes(const rbsm_request &r) {
+// Arena bytes of a request: every per-light result not written in place, and
+// the composite when it is staged.
+int64_t request_bytes(const EngineReq &R) {
+    const rbsm_request &r = R.req;
     int64_t b = 0;
-    for (int l = 0; l < r.n_lights; ++l) b += rbsm::Arena::round_up(r.n * (r.lights[l].mode == 0 ? 1 : 4));
-    if (r.composite_host) b += rbsm::Arena::round_up(r.n * 4);
+    for (int l = 0; l < r.n_lights; ++l)
+        if (!R.direct_out[l]) b += rbsm::Arena::round_up(r.n * (r.lights[l].mode == 0 ? 1 : 4));
+    if (r.composite && !R.direct_comp) b += rbsm::Arena::round_up(r.n * 4);
     return b;
+}
+
+// Is p device memory of `device` (so kernels may write it in place)?
+bool is_device_memory(const void *p, int device) {
+    if (!p) return false;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // pageable host memory reports an error; clear it
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice && a.device == device;
 }
 
 }  // namespace
@@ -163,7 +180,6 @@ struct rbsm_engine {
     int32_t max_inflight = 1;
     hipStream_t s_compute = nullptr, s_copy = nullptr;
     Slot slots[rbsm::kServeSlots];
-    std::vector<std::vector<EngineReq *>> slot_reqs = std::vector<std::vector<EngineReq *>>(rbsm::kServeSlots);
 
     std::mutex mu;  // guards everything below
     std::condition_variable cv_work, cv_done;
@@ -186,15 +202,11 @@ struct rbsm_engine {
 
 namespace {
 
-// Build one scheduling step's tables for the admitted requests and enqueue
-// it.  Returns false when nothing could be launched (no free slot).
+// A free step slot (at most kServeSlots steps have compute pending), or -1.
 int pick_slot(rbsm_engine *E) {
-    int pending = 0, free_slot = -1;
-    for (int s = 0; s < rbsm::kServeSlots; ++s) {
-        if (E->slots[s].busy) ++pending;
-        else if (free_slot < 0) free_slot = s;
-    }
-    return pending < rbsm::kServeComputeAhead ? free_slot : -1;
+    for (int s = 0; s < rbsm::kServeSlots; ++s)
+        if (!E->slots[s].busy) return s;
+    return -1;
 }
 
 }  // namespace
@@ -216,89 +228,103 @@ bool rbsm_engine::step_launch() {
     if (s < 0 || admitted.empty()) return false;
     Slot &S = slots[s];
     std::vector<EngineReq *> batch;
-    std::vector<std::pair<EngineReq *, int>> rpcf_jobs;
-    int n_jobs = 0, n_comp = 0;
-    int64_t tiles = 0, comp_blocks = 0;
+    std::vector<std::pair<EngineReq *, int>> rpcf_jobs, tile_jobs[2];  // [0] hard, [1] RSMSS
+    std::vector<rbsm::CompJob> comps;
+    int n_jobs = 0;
     size_t taken = 0;
     for (; taken < admitted.size(); ++taken) {
         EngineReq *R = admitted[taken];
         const rbsm_request &q = R->req;
-        int tile_jobs = 0;
-        for (int l = 0; l < q.n_lights; ++l) tile_jobs += (q.lights[l].kernel_radius == 0);
-        if (n_jobs + tile_jobs > rbsm::kServeMaxJobs || (int)batch.size() >= rbsm::kServeMaxReqs) break;
+        if (n_jobs + q.n_lights > rbsm::kServeMaxJobs || (int)batch.size() >= rbsm::kServeMaxReqs) break;
+        n_jobs += q.n_lights;
         for (int l = 0; l < q.n_lights; ++l) {
-            const rbsm_request_light &L = q.lights[l];
-            if (L.kernel_radius > 0) {
-                rpcf_jobs.push_back({R, l});
-                continue;
-            }
-            const JobLayout lay = job_layout(q.n, q.view_width, kDefaultTile.tile_w);
-            JobDev &D = S.h_jobs[n_jobs++];
-            D.m = R->maps[l];
-            D.frags = L.frags;
-            D.out = R->d_out[l];
-            D.n = q.n;
-            D.vw = lay.vw;
-            D.tiles_x = lay.tiles_x;
-            D.tile_base = tiles;
-            D.bias = L.depth_bias;
-            D.maxd = L.max_dist;
-            D.mode = L.mode;
-            D.vec_ok = ((uintptr_t)L.frags % 16 == 0) && (lay.vw % 4 == 0);  // arena outputs are 256-aligned
-            tiles += lay.tiles;
+            if (q.lights[l].kernel_radius > 0) rpcf_jobs.push_back({R, l});
+            else tile_jobs[q.lights[l].mode].push_back({R, l});
         }
-        if (R->d_comp) {
-            rbsm::CompJob &C = S.h_comp[n_comp++];
+        if (R->d_comp && q.n > 0) {
+            rbsm::CompJob C{};
             C.n_lights = q.n_lights;
             C.n = q.n;
             C.out = R->d_comp;
-            C.block_base = comp_blocks;
             for (int l = 0; l < q.n_lights; ++l) {
                 C.vis[l] = R->d_out[l];
                 C.w[l] = q.lights[l].weight;
                 C.hard[l] = q.lights[l].mode == 0;
             }
-            comp_blocks += rbsm::composite_blocks(q.n);
+            comps.push_back(C);
         }
         batch.push_back(R);
     }
     if (batch.empty()) return false;
     admitted.erase(admitted.begin(), admitted.begin() + taken);
 
-    hipError_t e = hipSuccess;
-    if (n_jobs > 0)
-        e = hipMemcpyAsync(S.d_jobs, S.h_jobs, sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, s_compute);
-    if (e == hipSuccess && n_comp > 0)
-        e = hipMemcpyAsync(S.d_comp, S.h_comp, sizeof(rbsm::CompJob) * n_comp, hipMemcpyHostToDevice, s_compute);
-    if (e != hipSuccess) {
-        fail_all("engine: table upload", e);
-        return false;
-    }
-    if (tiles > 0) {
-        const size_t lds = (size_t)kDefaultTile.cap * sizeof(float);
-        hipLaunchKernelGGL(rbsm::serve_kernel<32>, dim3((unsigned)tiles), dim3(kT), lds, s_compute, S.d_jobs, n_jobs,
-                           kDefaultTile.apron, kDefaultTile.cap);
+    hipError_t e = hipEventRecord(S.compute_start, s_compute);
+    const size_t lds = (size_t)kDefaultTile.cap * sizeof(float);
+    // tile jobs: per mode, in chunks that fit the kernel arguments
+    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+        const auto &list = tile_jobs[g];
+        for (size_t c0 = 0; c0 < list.size(); c0 += rbsm::kArgJobs) {
+            rbsm::ServeArgs A{};
+            int64_t tiles = 0;
+            for (size_t c = c0; c < list.size() && c < c0 + rbsm::kArgJobs; ++c) {
+                const EngineReq *R = list[c].first;
+                const rbsm_request &q = R->req;
+                const rbsm_request_light &L = q.lights[list[c].second];
+                const JobLayout lay = job_layout(q.n, q.view_width, kDefaultTile.tile_w);
+                if (lay.tiles == 0) continue;
+                JobDev &D = A.jobs[A.n_jobs];
+                D.m = R->maps[list[c].second];
+                D.frags = L.frags;
+                D.out = R->d_out[list[c].second];
+                D.n = q.n;
+                D.vw = lay.vw;
+                D.tiles_x = lay.tiles_x;
+                D.tile_base = 0;
+                D.bias = L.depth_bias;
+                D.maxd = L.max_dist;
+                D.mode = L.mode;
+                D.vec_ok = ((uintptr_t)L.frags % 16 == 0) && ((uintptr_t)D.out % (L.mode == 0 ? 4 : 16) == 0) &&
+                           (lay.vw % 4 == 0);
+                A.first[A.n_jobs++] = tiles;
+                tiles += lay.tiles;
+            }
+            if (tiles == 0) continue;
+            if (g == 0)
+                hipLaunchKernelGGL((rbsm::serve_kernel<true, 32>), dim3((unsigned)tiles), dim3(kT), lds, s_compute, A,
+                                   kDefaultTile.apron, kDefaultTile.cap);
+            else
+                hipLaunchKernelGGL((rbsm::serve_kernel<false, 32>), dim3((unsigned)tiles), dim3(kT), lds, s_compute,
+                                   A, kDefaultTile.apron, kDefaultTile.cap);
+        }
     }
     for (const auto &rj : rpcf_jobs) {
         const rbsm_request &q = rj.first->req;
         const rbsm_request_light &L = q.lights[rj.second];
+        if (q.n == 0) continue;
         launch_rpcf(rj.first->maps[rj.second], L.frags, q.n, q.view_width, L.depth_bias, L.max_dist, L.kernel_radius,
                     static_cast<float *>(rj.first->d_out[rj.second]), s_compute);
     }
-    if (comp_blocks > 0)
-        hipLaunchKernelGGL(rbsm::composite_batch_kernel, dim3((unsigned)comp_blocks), dim3(rbsm::kCompT), 0, s_compute,
-                           S.d_comp, n_comp);
-    e = hipGetLastError();
+    for (size_t c0 = 0; c0 < comps.size(); c0 += rbsm::kArgComp) {
+        rbsm::CompArgs A{};
+        int64_t blocks = 0;
+        for (size_t c = c0; c < comps.size() && c < c0 + rbsm::kArgComp; ++c) {
+            A.jobs[A.n_jobs] = comps[c];
+            A.first[A.n_jobs++] = blocks;
+            blocks += rbsm::composite_blocks(comps[c].n);
+        }
+        hipLaunchKernelGGL(rbsm::composite_batch_kernel, dim3((unsigned)blocks), dim3(rbsm::kCompT), 0, s_compute, A);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(S.compute_done, s_compute);
     if (e == hipSuccess) e = hipStreamWaitEvent(s_copy, S.compute_done, 0);
     for (EngineReq *R : batch) {
         const rbsm_request &q = R->req;
         for (int l = 0; l < q.n_lights && e == hipSuccess; ++l)
-            if (q.lights[l].out_host && q.n > 0)
-                e = hipMemcpyAsync(q.lights[l].out_host, R->d_out[l], (size_t)q.n * (q.lights[l].mode == 0 ? 1 : 4),
-                                   hipMemcpyDeviceToHost, s_copy);
-        if (e == hipSuccess && R->d_comp && q.n > 0)
-            e = hipMemcpyAsync(q.composite_host, R->d_comp, (size_t)q.n * 4, hipMemcpyDeviceToHost, s_copy);
+            if (q.lights[l].out && !R->direct_out[l] && q.n > 0)
+                e = hipMemcpyAsync(q.lights[l].out, R->d_out[l], (size_t)q.n * (q.lights[l].mode == 0 ? 1 : 4),
+                                   hipMemcpyDefault, s_copy);
+        if (e == hipSuccess && q.composite && !R->direct_comp && q.n > 0)
+            e = hipMemcpyAsync(q.composite, R->d_comp, (size_t)q.n * 4, hipMemcpyDefault, s_copy);
         if (e == hipSuccess) e = hipEventRecord(R->done, s_copy);
         inflight.push_back(R);
     }
@@ -307,17 +333,17 @@ bool rbsm_engine::step_launch() {
         return false;
     }
     S.busy = true;
-    slot_reqs[s] = batch;
     {
         std::lock_guard<std::mutex> lk(mu);
         stats.launches += 1;
-        stats.jobs_launched += n_jobs + (int64_t)rpcf_jobs.size();
+        stats.jobs_launched += n_jobs;
     }
     return true;
 }
 
 void rbsm_engine::run() {
     (void)hipSetDevice(device);
+    Clock::time_point idle_since{};
     for (;;) {
         bool progress = false;
         // steps whose compute finished free their table slot
@@ -325,8 +351,13 @@ void rbsm_engine::run() {
             if (!slots[s].busy) continue;
             const hipError_t q = hipEventQuery(slots[s].compute_done);
             if (q == hipSuccess) {
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, slots[s].compute_start, slots[s].compute_done);
                 slots[s].busy = false;
-                slot_reqs[s].clear();
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    stats.gpu_busy_ns += (int64_t)(ms * 1e6);
+                }
                 progress = true;
             } else if (q != hipErrorNotReady) {
                 fail_all("engine: compute", q);
@@ -340,7 +371,7 @@ void rbsm_engine::run() {
                 ++i;
                 continue;
             }
-            arena.release(R->off, R->bytes);
+            if (R->bytes > 0) arena.release(R->off, R->bytes);
             std::lock_guard<std::mutex> lk(mu);
             R->t_done = Clock::now();
             R->status = q == hipSuccess ? 1 : RBSM_ERR_HIP;
@@ -358,15 +389,20 @@ void rbsm_engine::run() {
             std::lock_guard<std::mutex> lk(mu);
             while (!queue.empty() && (int64_t)(admitted.size() + inflight.size()) < max_inflight) {
                 EngineReq *R = queue.front();
-                const int64_t off = arena.alloc(R->bytes);
+                const int64_t off = R->bytes > 0 ? arena.alloc(R->bytes) : 0;  // nothing staged: no block
                 if (off < 0) break;
                 R->off = off;
                 char *p = d_arena + off;
                 for (int l = 0; l < R->req.n_lights; ++l) {
+                    if (R->direct_out[l]) {
+                        R->d_out[l] = R->req.lights[l].out;
+                        continue;
+                    }
                     R->d_out[l] = p;
                     p += rbsm::Arena::round_up(R->req.n * (R->req.lights[l].mode == 0 ? 1 : 4));
                 }
-                R->d_comp = R->req.composite_host ? reinterpret_cast<float *>(p) : nullptr;
+                R->d_comp = R->direct_comp ? R->req.composite
+                                           : (R->req.composite ? reinterpret_cast<float *>(p) : nullptr);
                 queue.pop_front();
                 admitted.push_back(R);
                 stats.queued -= 1;
@@ -377,12 +413,27 @@ void rbsm_engine::run() {
         }
         if (step_launch()) progress = true;
         if (!progress) {
+            // with work on the device, poll (yielding the core); idle, sleep
+            // until a submission arrives
+            if (!admitted.empty() || !inflight.empty()) {
+                std::this_thread::yield();
+                idle_since = Clock::time_point{};
+                continue;
+            }
             std::unique_lock<std::mutex> lk(mu);
-            if (stop && queue.empty() && admitted.empty() && inflight.empty()) break;
-            if (queue.empty() && admitted.empty() && inflight.empty())
-                cv_work.wait(lk, [&] { return stop || !queue.empty(); });
-            else
-                cv_work.wait_for(lk, std::chrono::microseconds(20));
+            if (stop && queue.empty()) break;
+            if (!queue.empty()) continue;
+            // idle: keep polling for a short while (a request arriving now is
+            // picked up at once), then sleep until a submission
+            const auto now = Clock::now();
+            if (idle_since == Clock::time_point{}) idle_since = now;
+            if (now - idle_since < std::chrono::microseconds(500)) {
+                lk.unlock();
+                std::this_thread::yield();
+                continue;
+            }
+            cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+            idle_since = Clock::time_point{};
         }
     }
 }

@@ -59,13 +59,19 @@ def world(rb):
     return dict(maps=lights, dev_maps=dev_maps, frags=frags, dev_frags=dev_frags, views=views, reqs=reqs)
 
 
-def _outs(world, req, pinned=True):
+def _outs(world, req, where="pinned"):
+    """Result buffers: pinned host, pageable host, or device (written in place)."""
     w, h = world["views"][req["view"]]
     n = w * h
-    outs = [torch.empty(n, dtype=torch.uint8 if L["mode"] == 0 else torch.float32).pin_memory() if pinned
-            else torch.empty(n, dtype=torch.uint8 if L["mode"] == 0 else torch.float32) for L in req["lights"]]
-    comp = torch.empty(n, dtype=torch.float32).pin_memory() if pinned else torch.empty(n, dtype=torch.float32)
-    return n, w, outs, comp
+
+    def buf(dtype):
+        if where == "device":
+            return torch.full((n,), 7, dtype=dtype, device="cuda")
+        t = torch.empty(n, dtype=dtype)
+        return t.pin_memory() if where == "pinned" else t
+
+    outs = [buf(torch.uint8 if L["mode"] == 0 else torch.float32) for L in req["lights"]]
+    return n, w, outs, buf(torch.float32)
 
 
 def _submit(eng, ids, world, req, outs, comp):
@@ -76,13 +82,13 @@ def _submit(eng, ids, world, req, outs, comp):
     return eng.submit(w * h, lights, view_width=w, composite=comp)
 
 
-def _run(rb, world, budget, max_inflight, burst):
+def _run(rb, world, budget, max_inflight, burst, where="pinned"):
     eng = rb.Engine(budget, max_inflight)
     ids = [eng.add_light(m) for m in world["dev_maps"]]
     results = []
     tickets = []
     for req in world["reqs"]:
-        n, w, outs, comp = _outs(world, req)
+        n, w, outs, comp = _outs(world, req, where)
         t = _submit(eng, ids, world, req, outs, comp)
         if burst:
             tickets.append(t)
@@ -93,7 +99,7 @@ def _run(rb, world, budget, max_inflight, burst):
         assert eng.wait(t, 60000) is not None
     st = eng.stats()
     eng.close()
-    return [([o.numpy().copy() for o in outs], comp.numpy().copy()) for outs, comp in results], st
+    return [([o.cpu().numpy().copy() for o in outs], comp.cpu().numpy().copy()) for outs, comp in results], st
 
 
 def _plain(rb, world, req):
@@ -138,6 +144,16 @@ def test_alone_and_in_the_mix_are_identical(rb, world):
         for x, y in zip(oa, om):
             assert np.array_equal(x, y), k
         assert np.array_equal(ca, cm), k
+    # results written in place on the device (no staging) and to pageable host
+    # memory: the same values again
+    say("serving: device and pageable destinations")
+    dev, st_d = _run(rb, world, budget=1 << 20, max_inflight=6, burst=True, where="device")
+    assert st_d["arena_peak_bytes"] == 0                  # nothing staged
+    page, _ = _run(rb, world, budget=2 << 20, max_inflight=6, burst=True, where="pageable")
+    for k in range(len(alone)):
+        for x, y, z in zip(alone[k][0], dev[k][0], page[k][0]):
+            assert np.array_equal(x, y) and np.array_equal(x, z), k
+        assert np.array_equal(alone[k][1], dev[k][1]) and np.array_equal(alone[k][1], page[k][1]), k
     say("serving: plain entry points")
     for k, req in enumerate(world["reqs"]):
         po, pc = _plain(rb, world, req)
@@ -185,6 +201,8 @@ def test_engine_rejections_and_empty_request(rb, world):
         eng.submit(n, [dict(light=lid, mode=0, frags=f, kernel_radius=2)])
     with pytest.raises(rb.RbsmError):
         eng.wait(12345, 10)
+    with pytest.raises(rb.RbsmError):   # a device result buffer over the fragments
+        eng.submit(n, [dict(light=lid, mode=1, frags=f, out=f.view(-1)[:n])])
     empty = torch.empty(0, 3, dtype=torch.float32, device="cuda")
     t = eng.submit(0, [dict(light=lid, mode=0, frags=empty)])
     assert eng.wait(t, 10000) is not None
