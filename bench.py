@@ -398,6 +398,29 @@ def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: 
     }
 
 
+def raster_section(torch, rb, seed: int = 5001, reps: int = 10):
+    """On-device shadow-map rasterization of the serving lights' scenes
+    (64-triangle scenes, 1024^2..8192^2): time per map and texel rate; the
+    pass writes 4 bytes per texel."""
+    import synth
+    res = {}
+    for S in (1024, 2048, 4096, 8192):
+        sc = synth.triangle_scene(seed * 10 + {1024: 0, 2048: 1, 4096: 2, 8192: 3}[S], S, S, 64)
+        prims, rec = sc.primitives()
+        dp = torch.from_numpy(np.ascontiguousarray(prims).view(np.uint8).copy()).cuda()
+        out = torch.empty((S, S), dtype=torch.float32, device="cuda")
+        rb.rbsm_rasterize(dp, rec, S, S, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rb.rbsm_rasterize(dp, rec, S, S, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{S}x{S}"] = {"ms": ms, "texels_per_s": S * S / (ms * 1e-3), "write_GBps": 4 * S * S / (ms * 1e-3) / 1e9}
+    return {"workload": "64 random triangles over a tilted receiver, binary64 coverage", "maps": res}
+
+
 def cpu_baseline(frames: Frames, budget_s: float):
     """Oracle (single-threaded C) on a bounded sample of the same frames."""
     import oracle
@@ -535,6 +558,8 @@ def main():
         out["batched"] = batched_section(torch, rb)
         torch.cuda.empty_cache()
         out["serving"] = serving_section(torch, rb)
+        torch.cuda.empty_cache()
+        out["raster"] = raster_section(torch, rb)
         torch.cuda.empty_cache()
         frames = Frames.__new__(Frames)  # host frames for the CPU leg
         import synth

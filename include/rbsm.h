@@ -194,6 +194,40 @@ int64_t rbsm_plan_fragments(const rbsm_plan *plan);
 void rbsm_plan_destroy(rbsm_plan *plan);
 
 /*
+ * Shadow-map rasterization on the device: the light pass that produces the
+ * depth map the pass consumes (Sec. 2 takes it as given), so a frame can stay
+ * on the GPU from scene to visibility.
+ *
+ * Texel (i, j) samples its centre u = (i + 0.5) / width, v = (j + 0.5) /
+ * height and stores the nearest surface there: the minimum of the receiver
+ * plane r0 + ru (u - 0.5) + rv (v - 0.5) (evaluated in binary64, rounded to
+ * binary32) and the depth of every primitive covering the centre.  A convex
+ * polygon (vertices counter-clockwise in (u, v)) covers a point when no edge
+ * function (b - a) x (p - a) is negative and each zero lies on an edge that
+ * runs downwards or horizontally to the left (top-left tie rule); a slab
+ * covers o <= nx u + ny v < o + w.  Coverage is decided in binary64 without
+ * contraction.  Primitives of another kind or vertex count cover nothing.
+ */
+typedef struct {
+    int32_t kind;        /* 0: convex polygon, 1: slab */
+    int32_t nv;          /* polygon vertex count, 3 or 4 */
+    double x[4], y[4];   /* polygon vertices in texture coordinates */
+    double nx, ny, o, w; /* slab: unit normal and the covered range of n.p */
+    float depth;         /* constant light-space depth */
+    int32_t pad;         /* unused */
+} rbsm_prim;             /* 112 bytes */
+
+/*
+ *   prims       [n_prims] device array of rbsm_prim, read only
+ *   n_prims     >= 0
+ *   r0, ru, rv  receiver plane
+ *   shadow_map  [height*pitch] float32 device output, row-major (columns >=
+ *               width untouched); must not overlap prims
+ */
+int rbsm_rasterize(const rbsm_prim *prims, int32_t n_prims, double r0, double ru, double rv, int32_t width,
+                   int32_t height, int64_t pitch, float *shadow_map, hipStream_t stream);
+
+/*
  * Multi-light compositing: one shadow value per fragment of a view lit by
  * several lights, the weighted sum of the per-light visibilities,
  *   out[k] = sum over l in order of weights[l] * vis_l[k]
@@ -290,7 +324,8 @@ void rbsm_engine_destroy(rbsm_engine *engine);
 /* Message for the calling thread's last non-zero return ("" if none). */
 const char *rbsm_last_error(void);
 
-/* ABI version: 100 * major + minor (1.01: compositing and the serving engine). */
+/* ABI version: 100 * major + minor (1.02: compositing, the serving engine and
+ * rasterization). */
 int32_t rbsm_abi_version(void);
 
 #ifdef __cplusplus

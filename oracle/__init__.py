@@ -71,6 +71,11 @@ def _load():
     lib.oracle_fetch_count.restype = ctypes.c_int64
     lib.oracle_composite.argtypes = [i64, ctypes.c_int, vp, vp, vp, vp]
     lib.oracle_composite.restype = ctypes.c_int
+    d = ctypes.c_double
+    lib.oracle_raster.argtypes = [vp, ctypes.c_int, d, d, d, ctypes.c_int, ctypes.c_int, i64, vp]
+    lib.oracle_raster.restype = ctypes.c_int
+    lib.oracle_raster_texels.argtypes = [vp, ctypes.c_int, d, d, d, ctypes.c_int, ctypes.c_int, vp, vp, i64, vp]
+    lib.oracle_raster_texels.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -192,4 +197,35 @@ def composite(vis: list, weights) -> np.ndarray:
     out = np.empty(n, np.float32)
     _check(_load().oracle_composite(n, len(arrs), ptrs, hard.ctypes.data, w.ctypes.data, out.ctypes.data),
            "composite")
+    return out
+
+
+# Primitive record of oracle_raster (112 bytes; the same field layout as the
+# generator's export).
+PRIM_DTYPE = np.dtype([("kind", "<i4"), ("nv", "<i4"), ("x", "<f8", (4,)), ("y", "<f8", (4,)),
+                       ("nx", "<f8"), ("ny", "<f8"), ("o", "<f8"), ("w", "<f8"), ("depth", "<f4"),
+                       ("pad", "<i4")])
+
+
+def raster(prims: np.ndarray, receiver, width: int, height: int) -> np.ndarray:
+    """Shadow-map rasterization: float32 [height, width] of the nearest
+    surface at each texel centre (receiver plane or covering primitive)."""
+    p = np.ascontiguousarray(prims, dtype=PRIM_DTYPE)
+    out = np.empty((height, width), np.float32)
+    r0, ru, rv = receiver
+    _check(_load().oracle_raster(p.ctypes.data if len(p) else None, len(p), r0, ru, rv, width, height, width,
+                                 out.ctypes.data), "raster")
+    return out
+
+
+def raster_texels(prims: np.ndarray, receiver, width: int, height: int, ti: np.ndarray, tj: np.ndarray) -> np.ndarray:
+    """``raster`` at chosen texels (column ti[k], row tj[k]): float32 [count]."""
+    p = np.ascontiguousarray(prims, dtype=PRIM_DTYPE)
+    i32 = np.ascontiguousarray(ti, np.int32)
+    j32 = np.ascontiguousarray(tj, np.int32)
+    out = np.empty(len(i32), np.float32)
+    r0, ru, rv = receiver
+    _check(_load().oracle_raster_texels(p.ctypes.data if len(p) else None, len(p), r0, ru, rv, width, height,
+                                        i32.ctypes.data, j32.ctypes.data, len(i32), out.ctypes.data),
+           "raster_texels")
     return out

@@ -412,3 +412,70 @@ int oracle_composite(int64_t n, int n_lights, const void *const *vis, const int3
     }
     return 0;
 }
+
+/* Shadow-map rasterization (on-device extension): the light pass producing
+ * the depth map the shadow pass reads (Sec. 2 takes it as given).  A texel
+ * samples its centre ((i + 0.5) / W, (j + 0.5) / H) and keeps the nearest
+ * surface there: the receiver plane r0 + ru (u - .5) + rv (v - .5) (binary64,
+ * rounded to binary32) or the depth of any primitive covering the centre,
+ * whichever is smaller.  Polygons (convex, counter-clockwise) cover a point
+ * when each edge's cross product (b - a) x (p - a) is positive, or zero on an
+ * edge running downwards or horizontally to the left (top-left tie rule);
+ * slabs cover o <= n.p < o + w.  Record layout: 112 bytes,
+ * {int32 kind, int32 nv, double x[4], y[4], nx, ny, o, w, float depth, pad}. */
+typedef struct {
+    int32_t kind, nv;
+    double x[4], y[4];
+    double nx, ny, o, w;
+    float depth;
+    int32_t pad;
+} oracle_prim;
+
+static int prim_covers(const oracle_prim *q, double px, double py) {
+    if (q->kind == 1) {
+        const double t = q->nx * px + q->ny * py;
+        return t >= q->o && t < q->o + q->w;
+    }
+    if (q->kind != 0 || q->nv < 3 || q->nv > 4) return 0;
+    for (int a = 0; a < q->nv; ++a) {
+        const int b = (a + 1) % q->nv;
+        const double cross = (q->x[b] - q->x[a]) * (py - q->y[a]) - (q->y[b] - q->y[a]) * (px - q->x[a]);
+        if (cross > 0.0) continue;
+        if (cross < 0.0) return 0;
+        const double dx = q->x[b] - q->x[a], dy = q->y[b] - q->y[a];
+        const int owns = dy < 0.0 || (dy == 0.0 && dx < 0.0);
+        if (!owns) return 0;
+    }
+    return 1;
+}
+
+int oracle_raster(const oracle_prim *prims, int n, double r0, double ru, double rv, int W, int H, int64_t pitch,
+                  float *map) {
+    if (n < 0 || W < 1 || H < 1 || pitch < W) return -1;
+    for (int j = 0; j < H; ++j) {
+        const double v = (j + 0.5) / H;
+        for (int i = 0; i < W; ++i) {
+            const double u = (i + 0.5) / W;
+            float nearest = (float)(r0 + ru * (u - 0.5) + rv * (v - 0.5));
+            for (int k = 0; k < n; ++k)
+                if (prim_covers(&prims[k], u, v) && prims[k].depth < nearest) nearest = prims[k].depth;
+            map[(int64_t)j * pitch + i] = nearest;
+        }
+    }
+    return 0;
+}
+
+/* The same value at count chosen texels (i[k], j[k]) of a width x height map. */
+int oracle_raster_texels(const oracle_prim *prims, int n, double r0, double ru, double rv, int W, int H,
+                         const int32_t *ti, const int32_t *tj, int64_t count, float *out) {
+    if (n < 0 || W < 1 || H < 1) return -1;
+    for (int64_t k = 0; k < count; ++k) {
+        if (ti[k] < 0 || ti[k] >= W || tj[k] < 0 || tj[k] >= H) return -2;
+        const double u = (ti[k] + 0.5) / W, v = (tj[k] + 0.5) / H;
+        float nearest = (float)(r0 + ru * (u - 0.5) + rv * (v - 0.5));
+        for (int q = 0; q < n; ++q)
+            if (prim_covers(&prims[q], u, v) && prims[q].depth < nearest) nearest = prims[q].depth;
+        out[k] = nearest;
+    }
+    return 0;
+}

@@ -122,6 +122,9 @@ def load_library() -> ctypes.CDLL:
     lib.rbsm_plan_fragments.restype = ctypes.c_int64
     lib.rbsm_plan_destroy.argtypes = [vp]
     lib.rbsm_plan_destroy.restype = None
+    d = ctypes.c_double
+    lib.rbsm_rasterize.argtypes = [vp, ctypes.c_int32, d, d, d, ctypes.c_int32, ctypes.c_int32, i64, vp, vp]
+    lib.rbsm_rasterize.restype = ctypes.c_int
     lib.rbsm_composite.argtypes = [i64, ctypes.c_int32, vp, vp, vp, vp, vp]
     lib.rbsm_composite.restype = ctypes.c_int
     lib.rbsm_engine_create.argtypes = [i64, ctypes.c_int32, PP]
@@ -334,6 +337,30 @@ class Plan:
         self.close()
 
 
+PRIM_BYTES = 112  # sizeof(rbsm_prim)
+
+
+def rbsm_rasterize(prims: torch.Tensor, receiver, width: int, height: int, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """Rasterize primitives (a device uint8 tensor holding rbsm_prim records,
+    e.g. ``torch.from_numpy(records.view(np.uint8)).cuda()``) over the receiver
+    plane (r0, ru, rv) into a float32 [height, width] depth map (or into
+    ``out``, a 2-D device tensor with contiguous rows)."""
+    if prims.device.type != "cuda" or prims.dtype != torch.uint8 or not prims.is_contiguous() \
+            or prims.numel() % PRIM_BYTES:
+        raise RbsmError("rbsm_rasterize: prims must be contiguous device bytes of 112-byte records")
+    if out is None:
+        out = torch.empty((height, width), dtype=torch.float32, device=prims.device)
+    if out.device.type != "cuda" or out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1 \
+            or out.shape[0] < height or out.shape[1] < width:
+        raise RbsmError("rbsm_rasterize: out must be a float32 device map with contiguous rows")
+    n = prims.numel() // PRIM_BYTES
+    r0, ru, rv = receiver
+    _call("rbsm_rasterize", prims.data_ptr() if n else None, n, float(r0), float(ru), float(rv), int(width),
+          int(height), out.stride(0), out.data_ptr(), _stream(stream))
+    return out
+
+
 def rbsm_composite(vis: list, modes: list, weights: list, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Weighted sum of per-light visibilities (device tensors: uint8 masks for
     mode 0, float32 for mode 1) into one float32 tensor."""
@@ -457,5 +484,5 @@ class Engine:
         self.close()
 
 
-__all__ = ["Engine", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+__all__ = ["Engine", "rbsm_rasterize", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
            "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

@@ -18,6 +18,7 @@
 #include "rbsm_device.hpp"
 #include "tile_pass.hpp"
 #include "rpcf_pass.hpp"
+#include "raster_pass.hpp"
 
 using namespace rbsm;
 
@@ -494,6 +495,21 @@ void rbsm_plan_destroy(rbsm_plan *plan) {
     delete plan;
 }
 
+int rbsm_rasterize(const rbsm_prim *prims, int32_t n_prims, double r0, double ru, double rv, int32_t width,
+                   int32_t height, int64_t pitch, float *shadow_map, hipStream_t stream) {
+    const char *fn = "rbsm_rasterize";
+    if (width < 1 || height < 1 || width > 65536 || height > 65536)
+        return fail(RBSM_ERR_INVALID_ARG, "%s: width and height must be in 1..65536", fn);
+    if (pitch < width) return fail(RBSM_ERR_INVALID_ARG, "%s: pitch < width", fn);
+    if (n_prims < 0) return fail(RBSM_ERR_INVALID_ARG, "%s: n_prims < 0", fn);
+    if (!shadow_map || (n_prims > 0 && !prims)) return fail(RBSM_ERR_INVALID_ARG, "%s: null array pointer", fn);
+    const size_t map_bytes = ((size_t)(height - 1) * (size_t)pitch + (size_t)width) * 4u;
+    if (n_prims > 0 && overlaps(shadow_map, map_bytes, prims, (size_t)n_prims * sizeof(rbsm_prim)))
+        return fail(RBSM_ERR_INVALID_ARG, "%s: shadow_map overlaps prims", fn);
+    launch_raster(prims, n_prims, r0, ru, rv, width, height, pitch, shadow_map, stream);
+    return launched(fn);
+}
+
 int rbsm_composite(int64_t n, int32_t n_lights, const void *const *vis, const int32_t *modes, const float *weights,
                    float *out, hipStream_t stream) {
     const char *fn = "rbsm_composite";
@@ -699,6 +715,6 @@ void rbsm_engine_destroy(rbsm_engine *E) {
 
 const char *rbsm_last_error(void) { return g_err; }
 
-int32_t rbsm_abi_version(void) { return 101; }
+int32_t rbsm_abi_version(void) { return 102; }
 
 }  // extern "C"

@@ -64,6 +64,8 @@ def _load():
     lib.synth_frags_camera_rows.restype = ctypes.c_int
     lib.synth_uniform_f32.argtypes = [u64, i64, vp]
     lib.synth_uniform_f32.restype = None
+    lib.synth_scene_export.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.synth_scene_export.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -71,6 +73,15 @@ def _load():
 def _ptr(a: np.ndarray) -> int:
     assert a.flags["C_CONTIGUOUS"]
     return a.ctypes.data
+
+
+# One primitive of a blocker scene: kind 0 is a convex counter-clockwise
+# polygon of nv (3 or 4) vertices in texture coordinates, kind 1 a slab
+# o <= nx*u + ny*v < o + w; depth is the blocker's constant light-space depth.
+PRIM_DTYPE = np.dtype([("kind", "<i4"), ("nv", "<i4"), ("x", "<f8", (4,)), ("y", "<f8", (4,)),
+                       ("nx", "<f8"), ("ny", "<f8"), ("o", "<f8"), ("w", "<f8"), ("depth", "<f4"),
+                       ("pad", "<i4")])
+assert PRIM_DTYPE.itemsize == 112
 
 
 class Scene:
@@ -96,6 +107,15 @@ class Scene:
         out = np.zeros((self.height, pitch), dtype=np.float32)
         _load().synth_scene_raster(self._h, _ptr(out), pitch)
         return out
+
+    def primitives(self):
+        """The scene's primitives as a structured array (PRIM_DTYPE, 112 bytes
+        a record) and its receiver plane (r0, ru, rv)."""
+        n = self.n_prims
+        out = np.zeros(max(n, 1), dtype=PRIM_DTYPE)
+        rec = np.zeros(3, dtype=np.float64)
+        _load().synth_scene_export(self._h, out.ctypes.data, n, rec.ctypes.data)
+        return out[:n], (float(rec[0]), float(rec[1]), float(rec[2]))
 
     def camera_fragments(self, seed: int, width: int, height: int, vfov_deg: float = 40.0) -> np.ndarray:
         """Perspective-camera fragments, float32 [width*height, 3] = (u, v, z), screen row-major."""

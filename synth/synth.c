@@ -266,6 +266,34 @@ synth_scene *synth_scene_tris(uint64_t seed, int W, int H, int n_tris, int fence
     return sc;
 }
 
+/* Export the scene for other rasterizers: primitive k as the 112-byte record
+ * {int32 kind, int32 nv, double x[4], y[4], nx, ny, o, w, float depth, int32 pad}
+ * (kind 0: convex CCW polygon of nv vertices, 1: slab o <= nx*u + ny*v < o + w),
+ * and the receiver plane (r0, ru, rv).  Returns the primitive count. */
+typedef struct {
+    int32_t kind, nv;
+    double x[4], y[4];
+    double nx, ny, o, w;
+    float depth;
+    int32_t pad;
+} synth_prim_record;
+
+int synth_scene_export(const synth_scene *sc, void *records, int cap, double receiver[3]) {
+    synth_prim_record *out = (synth_prim_record *)records;
+    for (int k = 0; k < sc->n && k < cap; ++k) {
+        const synth_prim *q = &sc->p[k];
+        synth_prim_record *r = &out[k];
+        memset(r, 0, sizeof(*r));
+        r->kind = q->kind;
+        r->nv = q->nv;
+        for (int e = 0; e < 4; ++e) { r->x[e] = q->x[e]; r->y[e] = q->y[e]; }
+        r->nx = q->nx; r->ny = q->ny; r->o = q->o; r->w = q->w;
+        r->depth = (float)q->depth;
+    }
+    if (receiver) { receiver[0] = sc->r0; receiver[1] = sc->ru; receiver[2] = sc->rv; }
+    return sc->n;
+}
+
 /* Rasterize the scene into map[H][pitch] (float32).  Returns 0. */
 int synth_scene_raster(const synth_scene *sc, float *map, int64_t pitch) {
     const int W = sc->W, H = sc->H;

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.rbsm_abi_version() == 101
+    assert lib.rbsm_abi_version() == 102
 
 
 def _p(**kw):
@@ -149,3 +149,19 @@ def test_engine_arguments_validated_on_host(lib):
     assert lib.rbsm_engine_wait(None, 1, 0, None) == -1
     assert lib.rbsm_engine_get_stats(None, None) == -1
     lib.rbsm_engine_destroy(None)
+
+
+def test_rasterize_validated_on_host(lib):
+    d = ctypes.c_double
+    args = lambda **k: dict(dict(prims=0x100000, n=4, W=64, H=64, pitch=64, out=0x200000), **k)
+    def call(a):
+        return lib.rbsm_rasterize(a["prims"], a["n"], d(0.9), d(0.0), d(0.0), a["W"], a["H"], a["pitch"], a["out"],
+                                  None)
+    assert call(args(W=0)) == -1
+    assert call(args(H=70000)) == -1
+    assert call(args(pitch=10)) == -1
+    assert call(args(n=-1)) == -1
+    assert call(args(out=0)) == -1
+    assert call(args(prims=0)) == -1
+    assert call(args(out=0x100000 + 64)) == -1             # map over the primitive records
+    assert "overlap" in lib.rbsm_last_error().decode()

@@ -503,3 +503,108 @@ def test_composite_identities():
     assert np.array_equal(oracle.composite([v], [0.25]), v * np.float32(0.25))
     both = oracle.composite([v, h], [0.5, 0.5])
     assert np.max(np.abs(both.astype(np.float64) - 0.5 * (v + h))) <= 2 ** -24
+
+
+# --------------------------------------------------------------------------
+# Shadow-map rasterization (on-device extension)
+# --------------------------------------------------------------------------
+
+def _poly(xs, ys, depth):
+    r = np.zeros(1, oracle.PRIM_DTYPE)
+    r["kind"], r["nv"], r["depth"] = 0, len(xs), depth
+    r["x"][0, :len(xs)] = xs
+    r["y"][0, :len(ys)] = ys
+    return r
+
+
+def _slab(nx, ny, o, w, depth):
+    r = np.zeros(1, oracle.PRIM_DTYPE)
+    r["kind"], r["nx"], r["ny"], r["o"], r["w"], r["depth"] = 1, nx, ny, o, w, depth
+    return r
+
+
+def _exact_cover(prim, W, H):
+    """Coverage of texel centres in exact rational arithmetic (vertices on a
+    dyadic grid, so binary64 computes the same predicates exactly)."""
+    from fractions import Fraction as F
+    cov = np.zeros((H, W), bool)
+    xs = [F(float(v)) for v in prim["x"][:prim["nv"]]]
+    ys = [F(float(v)) for v in prim["y"][:prim["nv"]]]
+    for j in range(H):
+        py = F(2 * j + 1, 2 * H)
+        for i in range(W):
+            px = F(2 * i + 1, 2 * W)
+            inside = True
+            for a in range(prim["nv"]):
+                b = (a + 1) % prim["nv"]
+                c = (xs[b] - xs[a]) * (py - ys[a]) - (ys[b] - ys[a]) * (px - xs[a])
+                if c < 0 or (c == 0 and not (ys[b] - ys[a] < 0 or (ys[b] == ys[a] and xs[b] - xs[a] < 0))):
+                    inside = False
+                    break
+            cov[j, i] = inside
+    return cov
+
+
+def test_raster_receiver_plane_closed_form():
+    W, H = 37, 23
+    got = oracle.raster(np.zeros(0, oracle.PRIM_DTYPE), (0.9, 0.05, -0.03), W, H)
+    u = (np.arange(W) + 0.5) / W
+    v = (np.arange(H) + 0.5) / H
+    want = (0.9 + 0.05 * (u[None, :] - 0.5) + -0.03 * (v[:, None] - 0.5)).astype(np.float32)
+    assert np.array_equal(got, want)
+
+
+def test_raster_matches_exact_rational_coverage():
+    rng = np.random.default_rng(31)
+    W = H = 32
+    for _ in range(40):
+        pts = rng.integers(0, 1025, size=(3, 2)) / 1024.0   # dyadic vertices, exact in binary64
+        a = (pts[1, 0] - pts[0, 0]) * (pts[2, 1] - pts[0, 1]) - (pts[1, 1] - pts[0, 1]) * (pts[2, 0] - pts[0, 0])
+        if a == 0:
+            continue
+        if a < 0:
+            pts = pts[::-1]
+        prim = _poly(pts[:, 0], pts[:, 1], 0.5)
+        got = oracle.raster(prim, (0.9, 0.0, 0.0), W, H) == np.float32(0.5)
+        assert np.array_equal(got, _exact_cover(prim[0], W, H))
+
+
+def test_raster_shared_edges_are_watertight():
+    """A square cut along a diagonal: every centre inside the square is
+    covered by exactly one of the two halves, including centres on the cut."""
+    W = H = 64
+    # corners on texel centres, so centres (k + .5)/64 lie exactly on the cut
+    x0 = y0 = 8.5 / 64
+    x1 = y1 = 40.5 / 64
+    lower = _poly([x0, x1, x1], [y0, y0, y1], 0.3)           # CCW
+    upper = _poly([x0, x1, x0], [y0, y1, y1], 0.4)           # CCW
+    both = np.concatenate([lower, upper])
+    cl = oracle.raster(lower, (0.9, 0, 0), W, H) < 0.9
+    cu = oracle.raster(upper, (0.9, 0, 0), W, H) < 0.9
+    assert not np.any(cl & cu)
+    square = _poly([x0, x1, x1, x0], [y0, y0, y1, y1], 0.3)
+    cs = oracle.raster(square, (0.9, 0, 0), W, H) < 0.9
+    assert np.array_equal(cl | cu, cs)
+    assert np.any(np.diag(cl | cu))                          # centres on the cut are covered
+    # the nearer primitive wins where both could apply
+    m = oracle.raster(both, (0.9, 0, 0), W, H)
+    assert set(np.unique(m).tolist()) <= {np.float32(0.3), np.float32(0.4), np.float32(0.9)}
+
+
+def test_raster_slabs_cover_the_half_open_band():
+    W = H = 64
+    # vertical band 16/64 <= u < 24/64: texel columns 16..23 (their centres)
+    s = _slab(1.0, 0.0, 16 / 64, 8 / 64, 0.2)
+    cov = oracle.raster(s, (0.9, 0, 0), W, H) < 0.9
+    assert np.array_equal(np.nonzero(cov.any(axis=0))[0], np.arange(16, 24))
+    assert cov[:, 16:24].all()
+
+
+@pytest.mark.parametrize("fence", [False, True])
+def test_raster_agrees_with_the_scene_generator(fence):
+    sc = synth.triangle_scene(77 + fence, 200, 150, 24, fence=fence)
+    prims, rec = sc.primitives()
+    assert np.array_equal(oracle.raster(prims, rec, 200, 150), sc.raster())
+    q = synth.quad_scene(78, 128, 128)
+    prims, rec = q.primitives()
+    assert np.array_equal(oracle.raster(prims, rec, 128, 128), q.raster())
