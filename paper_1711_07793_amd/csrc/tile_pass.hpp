@@ -42,19 +42,35 @@ struct Staged {
 
 __device__ __forceinline__ int clampi(int x, int n) { return min(max(x, 0), n - 1); }
 
+typedef __attribute__((address_space(3))) float lds_float;  // a float in LDS
+
+constexpr int kStageChunk = 8;  // texels per thread whose loads are in flight together
+
 // Copy texels [y0, y0+h) x [x0, x0+w) of the map into dst (row-major, stride
-// w), the workgroup's kT threads striding over the rectangle.
+// w), the workgroup's kT threads striding over the rectangle.  Each thread
+// issues kStageChunk loads before its first LDS store, so a chunk of
+// kT * kStageChunk texels costs one memory round trip, not one per texel.
 __device__ __forceinline__ void stage_rect(const MapView &m, float *dst, int x0, int y0, int w, int h, int t) {
     const int area = w * h;
     int r = t / w, c = t % w;
     const int dr = kT / w, dc = kT % w;
-    for (int idx = t; idx < area; idx += kT) {
-        dst[idx] = m.t[(int64_t)(y0 + r) * m.pitch + (x0 + c)];
-        r += dr;
-        c += dc;
-        if (c >= w) {
-            c -= w;
-            ++r;
+    for (int base = 0; base < area; base += kT * kStageChunk) {
+        float v[kStageChunk];
+#pragma unroll
+        for (int u = 0; u < kStageChunk; ++u) {
+            const int idx = base + u * kT + t;
+            v[u] = idx < area ? m.t[(int64_t)(y0 + r) * m.pitch + (x0 + c)] : 0.0f;
+            r += dr;
+            c += dc;
+            if (c >= w) {
+                c -= w;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageChunk; ++u) {
+            const int idx = base + u * kT + t;
+            if (idx < area) dst[idx] = v[u];
         }
     }
 }
@@ -199,35 +215,48 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
         if (st.on) stage_rect(m, s_tex, st.bx0, st.by0, st.bw, bh, t);
         __syncthreads();
 
+        // centre and neighbour texels; the staged path reads through an LDS
+        // address-space pointer so its loads stay ds_reads (a merged generic
+        // pointer would make every read a 64-bit-addressed flat load)
+        float tc[kF][5];  // left, centre, right, top, bottom
+        if (st.on) {
+            const lds_float *lt = (const lds_float *)s_tex;
+#pragma unroll
+            for (int f = 0; f < kF; ++f) {
+                const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
+                const int il = max(ti - 1, 0), ir = min(ti + 1, m.W - 1);
+                const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
+                const int rc = (tj - st.by0) * st.bw - st.bx0;
+                const bool ok = valid[f];
+                tc[f][0] = ok ? lt[rc + il] : 0.0f;
+                tc[f][1] = ok ? lt[rc + ti] : 0.0f;
+                tc[f][2] = ok ? lt[rc + ir] : 0.0f;
+                tc[f][3] = ok ? lt[(jh - st.by0) * st.bw - st.bx0 + ti] : 0.0f;
+                tc[f][4] = ok ? lt[(jl - st.by0) * st.bw - st.bx0 + ti] : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < kF; ++f) {
+                const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
+                const int il = max(ti - 1, 0), ir = min(ti + 1, m.W - 1);
+                const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
+                const float *row = m.t + (int64_t)tj * m.pitch;
+                const bool ok = valid[f];
+                tc[f][0] = ok ? row[il] : 0.0f;
+                tc[f][1] = ok ? row[ti] : 0.0f;
+                tc[f][2] = ok ? row[ir] : 0.0f;
+                tc[f][3] = ok ? m.t[(int64_t)jh * m.pitch + ti] : 0.0f;
+                tc[f][4] = ok ? m.t[(int64_t)jl * m.pitch + ti] : 0.0f;
+            }
+        }
         bool s[kF], edge[kF];
         unsigned m0[kF];
 #pragma unroll
         for (int f = 0; f < kF; ++f) {
-            float cl = 0.0f, cc = 0.0f, cr = 0.0f, ct = 0.0f, cb = 0.0f;
-            if (valid[f]) {
-                const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
-                const int il = max(ti - 1, 0), ir = min(ti + 1, m.W - 1);
-                const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
-                if (st.on) {
-                    const int rc = (tj - st.by0) * st.bw - st.bx0;
-                    cl = s_tex[rc + il];
-                    cc = s_tex[rc + ti];
-                    cr = s_tex[rc + ir];
-                    ct = s_tex[(jh - st.by0) * st.bw - st.bx0 + ti];
-                    cb = s_tex[(jl - st.by0) * st.bw - st.bx0 + ti];
-                } else {
-                    const float *row = m.t + (int64_t)tj * m.pitch;
-                    cl = row[il];
-                    cc = row[ti];
-                    cr = row[ir];
-                    ct = m.t[(int64_t)jh * m.pitch + ti];
-                    cb = m.t[(int64_t)jl * m.pitch + ti];
-                }
-            }
             const float zb = ad[f].zb;
-            s[f] = lit(zb, cc);
-            m0[f] = ((lit(zb, cl) != s[f]) ? BIT_L : 0u) | ((lit(zb, cr) != s[f]) ? BIT_R : 0u) |
-                    ((lit(zb, ct) != s[f]) ? BIT_T : 0u) | ((lit(zb, cb) != s[f]) ? BIT_B : 0u);
+            s[f] = lit(zb, tc[f][1]);
+            m0[f] = ((lit(zb, tc[f][0]) != s[f]) ? BIT_L : 0u) | ((lit(zb, tc[f][2]) != s[f]) ? BIT_R : 0u) |
+                    ((lit(zb, tc[f][3]) != s[f]) ? BIT_T : 0u) | ((lit(zb, tc[f][4]) != s[f]) ? BIT_B : 0u);
             edge[f] = valid[f] && m0[f] != 0u && (!HARD || s[f]);
         }
 
@@ -333,9 +362,10 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
         if (v_on && d_hi == 4) stage_rect(m, s_v, vx0, vy0, vwid, vh, t);
         __syncthreads();
 
-        // 5. walks, one lane per (fragment, direction), blocks of kLdsSteps
-        //    steps with all reads of a block issued together (global memory
-        //    when the band did not fit)
+        // 5. walks, one lane per (fragment, direction): from the LDS band in
+        //    blocks of kLdsSteps steps with all reads of a block issued
+        //    together, or step by step from global memory when the band did
+        //    not fit
         const int nd = d_hi - d_lo;
         for (int task = t; task < nd * ne; task += kT) {
             const int e = task / nd, dir = d_lo + task % nd;
@@ -356,35 +386,49 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
             const int pa_x = horiz ? 0 : -1, pa_y = horiz ? 1 : 0;
             const int pb_x = horiz ? 0 : 1, pb_y = horiz ? -1 : 0;
             int rd = -(maxd + 1);
-            for (int k = 1; k <= maxd; k += kLdsSteps) {
-                float tc[kLdsSteps], ta[kLdsSteps], tb[kLdsSteps];
+            if (in_lds) {
+                // blocks of kLdsSteps steps, all reads of a block issued together
+                const lds_float *bl = (const lds_float *)band;
+                for (int k = 1; k <= maxd; k += kLdsSteps) {
+                    float tc[kLdsSteps], ta[kLdsSteps], tb[kLdsSteps];
 #pragma unroll
-                for (int u = 0; u < kLdsSteps; ++u) {
-                    const int ku = min(k + u, maxd);
-                    const int i = i0 + ku * dx, j = j0 + ku * dy;
-                    if (in_lds) {
-                        tc[u] = band[(clampi(j, m.H) - by0) * bstride + clampi(i, m.W) - bx0];
-                        ta[u] = band[(clampi(j + pa_y, m.H) - by0) * bstride + clampi(i + pa_x, m.W) - bx0];
-                        tb[u] = band[(clampi(j + pb_y, m.H) - by0) * bstride + clampi(i + pb_x, m.W) - bx0];
-                    } else {
-                        tc[u] = texel(m, i, j);
-                        ta[u] = texel(m, i + pa_x, j + pa_y);
-                        tb[u] = texel(m, i + pb_x, j + pb_y);
+                    for (int u = 0; u < kLdsSteps; ++u) {
+                        const int ku = min(k + u, maxd);
+                        const int i = i0 + ku * dx, j = j0 + ku * dy;
+                        tc[u] = bl[(clampi(j, m.H) - by0) * bstride + clampi(i, m.W) - bx0];
+                        ta[u] = bl[(clampi(j + pa_y, m.H) - by0) * bstride + clampi(i + pa_x, m.W) - bx0];
+                        tb[u] = bl[(clampi(j + pb_y, m.H) - by0) * bstride + clampi(i + pb_x, m.W) - bx0];
+                    }
+                    int stop = 0;
+#pragma unroll
+                    for (int u = kLdsSteps - 1; u >= 0; --u) {
+                        const int kk = k + u;
+                        if (kk > maxd) continue;
+                        const bool end = lit(zb, tc[u]) != s;
+                        const bool share = (chk_a && lit(zb, ta[u]) != s) || (chk_b && lit(zb, tb[u]) != s);
+                        if (end) stop = kk;
+                        else if (!share) stop = -kk;
+                    }
+                    if (stop != 0) {
+                        rd = stop;
+                        break;
                     }
                 }
-                int stop = 0;
-#pragma unroll
-                for (int u = kLdsSteps - 1; u >= 0; --u) {
-                    const int kk = k + u;
-                    if (kk > maxd) continue;
-                    const bool end = lit(zb, tc[u]) != s;
-                    const bool share = (chk_a && lit(zb, ta[u]) != s) || (chk_b && lit(zb, tb[u]) != s);
-                    if (end) stop = kk;
-                    else if (!share) stop = -kk;
-                }
-                if (stop != 0) {
-                    rd = stop;
-                    break;
+            } else {
+                // the band did not fit: one step at a time from global memory
+                // (rare; kept simple so it does not set the kernel's registers)
+                for (int k = 1; k <= maxd; ++k) {
+                    const int i = i0 + k * dx, j = j0 + k * dy;
+                    if (lit(zb, texel(m, i, j)) != s) {
+                        rd = k;
+                        break;
+                    }
+                    const bool share = (chk_a && lit(zb, texel(m, i + pa_x, j + pa_y)) != s) ||
+                                       (chk_b && lit(zb, texel(m, i + pb_x, j + pb_y)) != s);
+                    if (!share) {
+                        rd = -k;
+                        break;
+                    }
                 }
             }
             q_rd[e][dir] = (int8_t)rd;
