@@ -314,7 +314,7 @@ def test_tuning_never_changes_results(rb, tw, cap):
     p = c["params"]
     want_h = rb.rbsm_visibility(md, fd, p).cpu().numpy()
     want_s = rb.rsmss_visibility(md, fd, p).cpu().numpy()
-    for apron in (1, 4):
+    for apron in (1, 4, 8):
         t = rb.RbsmTuning(tw, apron, cap)
         assert np.array_equal(rb.rbsm_pass_tuned(0, md, fd, p, t).cpu().numpy(), want_h)
         assert np.array_equal(rb.rbsm_pass_tuned(1, md, fd, p, t).cpu().numpy(), want_s)
