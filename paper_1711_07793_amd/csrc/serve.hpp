@@ -290,10 +290,10 @@ bool rbsm_engine::step_launch() {
             }
             if (tiles == 0) continue;
             if (g == 0)
-                hipLaunchKernelGGL((rbsm::serve_kernel<true, 32>), dim3((unsigned)tiles), dim3(kT), lds, s_compute, A,
+                hipLaunchKernelGGL((rbsm::serve_kernel<true, kDefaultTile.tile_w>), dim3((unsigned)tiles), dim3(kT), lds, s_compute, A,
                                    kDefaultTile.apron, kDefaultTile.cap);
             else
-                hipLaunchKernelGGL((rbsm::serve_kernel<false, 32>), dim3((unsigned)tiles), dim3(kT), lds, s_compute,
+                hipLaunchKernelGGL((rbsm::serve_kernel<false, kDefaultTile.tile_w>), dim3((unsigned)tiles), dim3(kT), lds, s_compute,
                                    A, kDefaultTile.apron, kDefaultTile.cap);
         }
     }
