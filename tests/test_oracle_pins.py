@@ -224,6 +224,51 @@ def test_exhaustive_4x4_against_stencil(max_dist, hard):
     assert set(np.unique(rd_o[edge] > 0)) == {False, True}
 
 
+def _blob_maps(seed, n, H, W):
+    """Binary maps made of random overlapping rectangles: long runs, concave
+    corners, lines one texel thick and shapes touching the border."""
+    rng = np.random.default_rng(seed)
+    blocked = np.zeros((n, H, W), bool)
+    for k in range(n):
+        for _ in range(int(rng.integers(2, 12))):
+            x0, y0 = int(rng.integers(-4, W)), int(rng.integers(-4, H))
+            w = int(rng.integers(1, W // 2)) if rng.random() < 0.8 else 1
+            h = int(rng.integers(1, H // 2)) if rng.random() < 0.8 else 1
+            blocked[k, max(y0, 0):max(y0 + h, 0), max(x0, 0):max(x0 + w, 0)] ^= True
+    return blocked
+
+
+@pytest.mark.parametrize("max_dist,hard", [(3, True), (16, True), (40, True), (3, False), (40, False)])
+def test_random_blob_maps_against_stencil(max_dist, hard):
+    """Non-square odd-sized maps whose runs exceed the walk bound: the oracle
+    and the stencil form agree on every texel, walk and visibility."""
+    H, W, n_maps = 37, 45, 24
+    blocked = _blob_maps(1000 + max_dist + hard, n_maps, H, W)
+    maps = np.where(blocked, BLOCK, LIT).astype(np.float32)
+    S = (~blocked).astype(np.uint8)
+    rng = np.random.default_rng(2000 + max_dist)
+    mi = np.repeat(np.arange(n_maps, dtype=np.int32), H * W)
+    t = np.tile(np.arange(H * W), n_maps)
+    ti, tj = t % W, t // W
+    u = ((ti + rng.uniform(0, 1, ti.shape)) / W).astype(np.float32)
+    v = ((tj + rng.uniform(0, 1, tj.shape)) / H).astype(np.float32)
+    # the texel and fraction the oracle derives from (u, v) in binary32
+    X, Y = u * np.float32(W), v * np.float32(H)
+    ti, tj = np.floor(X).astype(np.int64), np.floor(Y).astype(np.int64)
+    ok = (ti < W) & (tj < H)
+    mi, ti, tj, u, v, X, Y = mi[ok], ti[ok], tj[ok], u[ok], v[ok], X[ok], Y[ok]
+    fx, fy = (X - np.floor(X)).astype(np.float32), (Y - np.floor(Y)).astype(np.float32)
+    frags = np.stack([u, v, np.full(u.shape, 0.9, np.float32)], 1).astype(np.float32)
+    vis_o, rd_o, nrd_o = oracle.multi(maps, mi, frags, params(W, H, max_dist=max_dist), hard)
+    vis_s, rd_s, nrd_s = stencil_rbsm.evaluate(S, mi, ti, tj, fx, fy, max_dist, hard)
+    assert np.array_equal(rd_o, rd_s)
+    assert np.array_equal(nrd_o, nrd_s)
+    assert np.array_equal(vis_o, vis_s)
+    # walks of every kind occur: ends, leaves and bound-exhausted ones
+    assert (rd_o > 0).any() and (rd_o < 0).any()
+    assert (rd_o == -(max_dist + 1)).any() == (max_dist < max(H, W))
+
+
 # --------------------------------------------------------------------------
 # Check (a): plain shadow mapping wherever no discontinuity exists
 # --------------------------------------------------------------------------
