@@ -1,7 +1,7 @@
 // Main hard / RSMSS (radius 0) pass for gfx950: 2-D screen tiles whose
 // light-space footprint is staged in LDS, edge fragments compacted with wave
-// ballots, traversals run one lane per (edge fragment, direction) from LDS
-// bands.  Included once, by rbsm.hip.
+// ballots, traversals run one lane per (edge fragment, direction) in blocks
+// of steps read from global memory.  Included once, by rbsm.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,8 +29,10 @@ __device__ __forceinline__ int64_t xcd_block(int b, int nb) {
 constexpr int kT = 256;            // threads per workgroup
 constexpr int kF = 4;              // consecutive pixels per thread
 constexpr int kTileF = kT * kF;    // fragments per tile
-constexpr int kState = 256;        // edge fragments whose full state is kept in LDS
-constexpr int kLdsSteps = 8;       // traversal steps per block, all reads issued together
+constexpr int kState = 128;        // edge fragments whose full state is kept in LDS
+constexpr int kWalkFirst = 2;     // steps every walk takes before the unfinished ones are compacted
+constexpr int kWalkSteps = 4;     // steps per block of a continued walk, all reads issued together
+constexpr int kCont = 512;         // continued walks queued per tile (more finish where they are)
 
 // Staged light-space footprint of one screen tile: texels [by0..by1] x
 // [bx0..bx1] of the map (clamped coordinates), row-major with stride bw.
@@ -114,6 +116,56 @@ __device__ __forceinline__ float fetch(const MapView &m, const Staged &st, int i
 // by which lane: every result equals the per-fragment listing.
 // Workgroup-shared state of one tile (the staged texels live in the dynamic
 // LDS array that follows it).
+// Bounded traversal (Listing 3) of one walk, a range of its steps at a time in
+// blocks of NB steps, every read of a block issued together.  The walk moves along one
+// coordinate p (clamped to [0, pmax]); the other coordinate is fixed for the
+// texel on the walk and for its two side neighbours (the texels of the
+// shared-discontinuity test), so a reader maps p to three texel values.
+// walk_range returns +k (the walk ends at step k) or -k (it leaves the
+// discontinuity at step k) for the first stopping step in [k0, k1], or 0.
+struct GlobalWalkReader {  // a map under 4 GiB in global memory
+    const char *t;           // map base (uniform)
+    unsigned c, a, b;        // byte offsets of the fixed coordinate
+    unsigned step4;          // bytes per unit of p
+    __device__ __forceinline__ void operator()(int p, float &tc, float &ta, float &tb) const {
+        const unsigned x = (unsigned)p * step4;
+        tc = *(const float *)(t + (c + x));
+        ta = *(const float *)(t + (a + x));
+        tb = *(const float *)(t + (b + x));
+    }
+};
+
+template <int NB, class Reader>
+__device__ __forceinline__ int walk_range(const Reader &rd3, int k0, int k1, int p0, int d, int pmax, float zb, bool s,
+                                          bool chk_a, bool chk_b) {
+    for (int k = k0; k <= k1; k += NB) {
+        float tc[NB], ta[NB], tb[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int ku = min(k + u, k1);
+            rd3(min(max(p0 + __mul24(ku, d), 0), pmax), tc[u], ta[u], tb[u]);
+        }
+        // bit u: step k+u ends the walk (a texel whose test differs from s:
+        // (zb > T) == s), or stops it (ends it, or shares no discontinuity
+        // direction with the fragment); the first stopping step decides
+        unsigned endb = 0, stopb = 0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const bool end = (zb > tc[u]) == s;
+            const bool share = (chk_a & ((zb > ta[u]) == s)) | (chk_b & ((zb > tb[u]) == s));
+            endb |= (unsigned)end << u;
+            stopb |= (unsigned)(end | !share) << u;
+        }
+        const int left = k1 - k + 1;
+        stopb &= left >= NB ? (1u << NB) - 1u : (1u << left) - 1u;
+        if (stopb != 0u) {
+            const int u = __builtin_ctz(stopb);
+            return (endb >> u) & 1u ? k + u : -(k + u);
+        }
+    }
+    return 0;
+}
+
 struct TileShared {
     int box[kT / 64][4];
     int16_t slot[kTileF];
@@ -121,7 +173,8 @@ struct TileShared {
     int qi[kState], qj[kState];
     float qz[kState], qfx[kState], qfy[kState];
     int8_t rd[kTileF][4];  // left, right, top, bottom
-    int count;
+    int16_t cont[kCont];   // walks (4 e + direction) continued after their first steps
+    int count, ncont;
 };
 
 template <bool HARD, int TW>
@@ -150,7 +203,6 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
     const unsigned long long below = __lanemask_lt();
 
     Staged st;
-    int core_i0, core_i1, core_j0, core_j1;  // clamped texel box of the tile's fragments
     {
         bool valid[kF];
 #pragma unroll
@@ -196,14 +248,16 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
             s_box[wave][0] = imin; s_box[wave][1] = imax;
             s_box[wave][2] = jmin; s_box[wave][3] = jmax;
         }
-        if (t == 0) q_count = 0;
+        if (t == 0) {
+            q_count = 0;
+            sh.ncont = 0;
+        }
         __syncthreads();
 #pragma unroll
         for (int w = 0; w < kT / 64; ++w) {
             imin = min(imin, s_box[w][0]); imax = max(imax, s_box[w][1]);
             jmin = min(jmin, s_box[w][2]); jmax = max(jmax, s_box[w][3]);
         }
-        core_i0 = imin; core_i1 = imax; core_j0 = jmin; core_j1 = jmax;
         st.lds = s_tex;
         st.bx0 = max(imin - apron, 0);
         st.bx1 = min(imax + apron, m.W - 1);
@@ -337,106 +391,102 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
         }
     };
 
-    // 4. restage: every texel a traversal of this tile can read lies in a
-    //    horizontal band (the core rows +-1, the core columns +-(maxd+1)) or
-    //    a vertical band (the core columns +-1, the core rows +-(maxd+1));
-    //    copy both into LDS over the core box when they fit
-    const int reach = maxd + 1;
-    const int hx0 = max(core_i0 - reach, 0), hx1 = min(core_i1 + reach, m.W - 1);
-    const int hy0 = max(core_j0 - 1, 0), hy1 = min(core_j1 + 1, m.H - 1);
-    const int vx0 = max(core_i0 - 1, 0), vx1 = min(core_i1 + 1, m.W - 1);
-    const int vy0 = max(core_j0 - reach, 0), vy1 = min(core_j1 + reach, m.H - 1);
-    const int hw = hx1 - hx0 + 1, hh = hy1 - hy0 + 1;
-    const int vwid = vx1 - vx0 + 1, vh = vy1 - vy0 + 1;
-    // both bands at once when they fit together, else one after the other
-    const bool both = (int64_t)hw * hh + (int64_t)vwid * vh <= (int64_t)cap;
-    const bool h_fits = (int64_t)hw * hh <= (int64_t)cap, v_fits = (int64_t)vwid * vh <= (int64_t)cap;
-    for (int pass = 0; pass < (both ? 1 : 2); ++pass) {
-        // pass covers directions [d_lo, d_hi): 0 left, 1 right, 2 top, 3 bottom
-        const int d_lo = both ? 0 : 2 * pass, d_hi = both ? 4 : 2 * pass + 2;
-        const bool h_on = both || (pass == 0 && h_fits);
-        const bool v_on = both || (pass == 1 && v_fits);
-        float *s_h = s_tex, *s_v = both ? s_tex + hw * hh : s_tex;
-        if (pass == 1) __syncthreads();  // pass 0 walks are done with s_tex
-        if (h_on && d_lo == 0) stage_rect(m, s_h, hx0, hy0, hw, hh, t);
-        if (v_on && d_hi == 4) stage_rect(m, s_v, vx0, vy0, vwid, vh, t);
-        __syncthreads();
-
-        // 5. walks, one lane per (fragment, direction): from the LDS band in
-        //    blocks of kLdsSteps steps with all reads of a block issued
-        //    together, or step by step from global memory when the band did
-        //    not fit
-        const int nd = d_hi - d_lo;
-        for (int task = t; task < nd * ne; task += kT) {
-            const int e = task / nd, dir = d_lo + task % nd;
-            int i0, j0;
-            float zb, fx, fy;
-            state_of(e, i0, j0, zb, fx, fy);
-            const unsigned sm = q_sm[e];
-            const bool s = (sm & 16u) != 0;
+    // walks, one lane per (fragment, direction), straight from global memory
+    // (L2) in blocks of steps whose reads are issued together; staging the
+    // walks' bands in LDS first measured slower.  Most walks stop within a
+    // few steps, so every walk first takes kWalkFirst steps; the unfinished
+    // ones are compacted into a queue and continued by as few waves as
+    // possible instead of holding every wave that has one of them.
+    const bool map_32 = (int64_t)m.pitch * m.H * 4 <= (int64_t)0xFFFFFFFFu;  // byte offsets fit 32 bits
+    struct Walk {
+        GlobalWalkReader r;
+        int p0, d, pmax;
+        float zb;
+        bool s, chk_a, chk_b;
+    };
+    // walk `task` = 4 e + direction (0 left, 1 right, 2 top, 3 bottom)
+    auto make_walk = [&](int task, int &i0, int &j0) -> Walk {
+        const int e = task >> 2, dir = task & 3;
+        float zb, fx, fy;
+        state_of(e, i0, j0, zb, fx, fy);
+        const unsigned sm = q_sm[e];
+        Walk w;
+        w.zb = zb;
+        w.s = HARD || (sm & 16u) != 0;  // the hard pass queues lit fragments only
+        const bool horiz = dir < 2;
+        w.d = dir == 0 || dir == 3 ? -1 : 1;
+        w.p0 = horiz ? i0 : j0;
+        w.pmax = (horiz ? m.W : m.H) - 1;
+        w.chk_a = horiz ? (sm & BIT_T) != 0 : (sm & BIT_L) != 0;
+        w.chk_b = horiz ? (sm & BIT_B) != 0 : (sm & BIT_R) != 0;
+        // the fixed coordinate of the walk's texel and of its side neighbours
+        // (rows j0, j0+1, j0-1 of a horizontal walk; columns i0, i0-1, i0+1 of
+        // a vertical one), clamped to the map
+        const int fc = horiz ? clampi(j0, m.H) : clampi(i0, m.W);
+        const int fa = horiz ? clampi(j0 + 1, m.H) : clampi(i0 - 1, m.W);
+        const int fb = horiz ? clampi(j0 - 1, m.H) : clampi(i0 + 1, m.W);
+        const unsigned fmul = horiz ? 4u * (unsigned)m.pitch : 4u;
+        w.r.t = (const char *)m.t;
+        w.r.c = (unsigned)fc * fmul;
+        w.r.a = (unsigned)fa * fmul;
+        w.r.b = (unsigned)fb * fmul;
+        w.r.step4 = horiz ? 4u : 4u * (unsigned)m.pitch;
+        return w;
+    };
+    const int first = min(kWalkFirst, maxd);
+    for (int task = t; task < 4 * ne; task += kT) {
+        int i0, j0;
+        const Walk w = make_walk(task, i0, j0);
+        int rd;
+        if (map_32) {
+            rd = walk_range<kWalkFirst>(w.r, 1, first, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
+            if (rd == 0 && first < maxd) {
+                const int slot = atomicAdd(&sh.ncont, 1);
+                if (slot < kCont) sh.cont[slot] = (int16_t)task;  // continued below
+                else rd = walk_range<kWalkSteps>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a,
+                                                 w.chk_b);
+                if (slot < kCont) continue;
+            }
+            if (rd == 0) rd = -(maxd + 1);
+        } else {
+            // a map of 4 GiB or more: one step at a time, 64-bit addresses
+            const int dir = task & 3;
             const int dx = dir == 0 ? -1 : (dir == 1 ? 1 : 0);
             const int dy = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
-            const bool horiz = dx != 0;
-            const bool chk_a = horiz ? (sm & BIT_T) != 0 : (sm & BIT_L) != 0;
-            const bool chk_b = horiz ? (sm & BIT_B) != 0 : (sm & BIT_R) != 0;
-            // band of this walk: rows (or columns) of the fragment +-1
-            const bool in_lds = horiz ? h_on : v_on;
-            const float *band = horiz ? s_h : s_v;
-            const int bx0 = horiz ? hx0 : vx0, by0 = horiz ? hy0 : vy0, bstride = horiz ? hw : vwid;
-            const int pa_x = horiz ? 0 : -1, pa_y = horiz ? 1 : 0;
-            const int pb_x = horiz ? 0 : 1, pb_y = horiz ? -1 : 0;
-            int rd = -(maxd + 1);
-            if (in_lds) {
-                // blocks of kLdsSteps steps, all reads of a block issued together
-                const lds_float *bl = (const lds_float *)band;
-                for (int k = 1; k <= maxd; k += kLdsSteps) {
-                    float tc[kLdsSteps], ta[kLdsSteps], tb[kLdsSteps];
-#pragma unroll
-                    for (int u = 0; u < kLdsSteps; ++u) {
-                        const int ku = min(k + u, maxd);
-                        const int i = i0 + ku * dx, j = j0 + ku * dy;
-                        tc[u] = bl[(clampi(j, m.H) - by0) * bstride + clampi(i, m.W) - bx0];
-                        ta[u] = bl[(clampi(j + pa_y, m.H) - by0) * bstride + clampi(i + pa_x, m.W) - bx0];
-                        tb[u] = bl[(clampi(j + pb_y, m.H) - by0) * bstride + clampi(i + pb_x, m.W) - bx0];
-                    }
-                    int stop = 0;
-#pragma unroll
-                    for (int u = kLdsSteps - 1; u >= 0; --u) {
-                        const int kk = k + u;
-                        if (kk > maxd) continue;
-                        const bool end = lit(zb, tc[u]) != s;
-                        const bool share = (chk_a && lit(zb, ta[u]) != s) || (chk_b && lit(zb, tb[u]) != s);
-                        if (end) stop = kk;
-                        else if (!share) stop = -kk;
-                    }
-                    if (stop != 0) {
-                        rd = stop;
-                        break;
-                    }
+            const int pa_x = dx != 0 ? 0 : -1, pa_y = dx != 0 ? 1 : 0;
+            const int pb_x = dx != 0 ? 0 : 1, pb_y = dx != 0 ? -1 : 0;
+            rd = -(maxd + 1);
+            for (int k = 1; k <= maxd; ++k) {
+                const int i = i0 + k * dx, j = j0 + k * dy;
+                if (lit(w.zb, texel(m, i, j)) != w.s) {
+                    rd = k;
+                    break;
                 }
-            } else {
-                // the band did not fit: one step at a time from global memory
-                // (rare; kept simple so it does not set the kernel's registers)
-                for (int k = 1; k <= maxd; ++k) {
-                    const int i = i0 + k * dx, j = j0 + k * dy;
-                    if (lit(zb, texel(m, i, j)) != s) {
-                        rd = k;
-                        break;
-                    }
-                    const bool share = (chk_a && lit(zb, texel(m, i + pa_x, j + pa_y)) != s) ||
-                                       (chk_b && lit(zb, texel(m, i + pb_x, j + pb_y)) != s);
-                    if (!share) {
-                        rd = -k;
-                        break;
-                    }
+                const bool share = (w.chk_a && lit(w.zb, texel(m, i + pa_x, j + pa_y)) != w.s) ||
+                                   (w.chk_b && lit(w.zb, texel(m, i + pb_x, j + pb_y)) != w.s);
+                if (!share) {
+                    rd = -k;
+                    break;
                 }
             }
-            q_rd[e][dir] = (int8_t)rd;
         }
+        q_rd[task >> 2][task & 3] = (int8_t)rd;
     }
     __syncthreads();
+    const int nc = min(sh.ncont, kCont);
+    if (nc > 0) {
+        for (int c = t; c < nc; c += kT) {
+            const int task = sh.cont[c];
+            int i0, j0;
+            const Walk w = make_walk(task, i0, j0);
+            const int rd = walk_range<kWalkSteps>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a,
+                                                  w.chk_b);
+            q_rd[task >> 2][task & 3] = (int8_t)(rd != 0 ? rd : -(maxd + 1));
+        }
+        __syncthreads();
+    }
 
-    // 6. normalize, evaluate and store, one lane per edge fragment
+    // normalize, evaluate and store, one lane per edge fragment
     for (int e = t; e < ne; e += kT) {
         int i0, j0;
         float zb, fx, fy;
@@ -450,10 +500,13 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
     }
 }
 
+// 8 waves per SIMD: 64 VGPRs (no spills) and, with the default LDS capacity,
+// 19 KB of LDS let 8 workgroups share a CU, so a 1080p frame's 2,040 tiles
+// are all resident at once (one round, no second prologue).
 template <bool HARD, int TW>
-__global__ __launch_bounds__(kT) void tile_kernel(MapView m, const float *__restrict__ frags, int64_t n,
-                                                  int64_t vw, int64_t tiles_x, float bias, int maxd, int apron,
-                                                  int cap, int vec_ok, void *__restrict__ out_v) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void tile_kernel(
+    MapView m, const float *__restrict__ frags, int64_t n, int64_t vw, int64_t tiles_x, float bias, int maxd,
+    int apron, int cap, int vec_ok, void *__restrict__ out_v) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
     process_tile<HARD, TW>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v,
