@@ -108,9 +108,11 @@ __global__ __launch_bounds__(kCompT) void composite_batch_kernel(const CompArgs 
 }
 
 // The batched tile pass of a scheduling step, one launch per mode and chunk of
-// jobs: each tile runs the code of the single-view pass.
+// jobs: each tile runs the code of the single-view pass, with its occupancy
+// (64 VGPRs, 8 workgroups per CU at the default LDS capacity).
 template <bool HARD, int TW>
-__global__ __launch_bounds__(kT) void serve_kernel(const ServeArgs a, int apron, int cap) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void serve_kernel(const ServeArgs a,
+                                                                                              int apron, int cap) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
