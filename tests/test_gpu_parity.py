@@ -284,6 +284,61 @@ def test_all_edge_fragments_fill_the_queue(rb):
         check_soft(m, f, p, rb.rsmss_visibility(dev(m), dev(f), p).cpu().numpy())
 
 
+@pytest.mark.parametrize("horizontal", [True, False])
+def test_long_walks_overflow_the_continuation_queue(rb, horizontal):
+    """Stripes one texel wide: every fragment is an edge fragment whose walks
+    along the stripe run to the bound, so the walks still running after their
+    first steps outnumber the continuation queue and the rest finish in place."""
+    W = 64
+    ii, jj = np.meshgrid(np.arange(W), np.arange(W))
+    m = np.where((jj if horizontal else ii) % 2 == 0, 0.5, 0.9).astype(np.float32)
+    rng = np.random.default_rng(12)
+    n = 4 * 1024 + 5
+    f = np.stack([rng.uniform(0, 1, n), rng.uniform(0, 1, n), np.full(n, 0.9)], 1).astype(np.float32)
+    for max_dist in (3, 30, 64):
+        p = dict(width=W, height=W, pitch=W, depth_bias=1e-4, max_dist=max_dist, kernel_radius=0)
+        say(f"stripes horizontal={horizontal} max_dist={max_dist}")
+        check_hard(m, f, p, rb.rbsm_visibility(dev(m), dev(f), p).cpu().numpy())
+        check_soft(m, f, p, rb.rsmss_visibility(dev(m), dev(f), p).cpu().numpy())
+
+
+def test_map_of_4_gib_takes_64_bit_walks(rb):
+    """A 32768 x 32768 map (2^32 bytes): texel offsets no longer fit 32 bits,
+    so walks step with 64-bit addresses.  Fragments sit on the edges of
+    blockers in the last rows (offsets past 4 GiB) and the first ones."""
+    S = 32768
+    say("4 GiB map: building")
+    m = np.full((S, S), 0.9, np.float32)
+    rng = np.random.default_rng(13)
+    rects = []
+    for k in range(40):
+        far = k % 2 == 0
+        y0 = int(rng.integers(S - 300, S - 20)) if far else int(rng.integers(0, 280))
+        x0 = int(rng.integers(0, S - 200))
+        h, w = int(rng.integers(1, 40)), int(rng.integers(1, 60))
+        m[y0:y0 + h, x0:x0 + w] = 0.5
+        rects.append((x0, y0, w, h))
+    # fragments on and next to the rectangles' borders
+    fr = []
+    for (x0, y0, w, h) in rects:
+        xs = rng.uniform(x0 - 3, x0 + w + 3, 2000)
+        ys = rng.uniform(y0 - 3, y0 + h + 3, 2000)
+        fr.append(np.stack([xs / S, ys / S], 1))
+    uv = np.concatenate(fr)
+    f = np.concatenate([uv, np.full((len(uv), 1), 0.7)], 1).astype(np.float32)
+    md = dev(m)
+    fd = dev(f)
+    for max_dist in (4, 40):
+        p = dict(width=S, height=S, pitch=S, depth_bias=1e-4, max_dist=max_dist, kernel_radius=0)
+        say(f"4 GiB map: max_dist={max_dist}")
+        check_hard(m, f, p, rb.rbsm_visibility(md, fd, p).cpu().numpy())
+        check_soft(m, f, p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
+        pr = dict(p, kernel_radius=2)
+        check_soft(m, f, pr, rb.rsmss_visibility(md, fd, pr).cpu().numpy())
+    del md
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("vw", [0, 1, 7, 240, 241, 1000])
 def test_layout_hint_never_changes_results(rb, vw):
     """view_width only changes how fragments are tiled (2-D tiles, partial
