@@ -4,16 +4,17 @@
 // rbsm.hip.
 //
 // Every term of one fragment tests texels against the same depth, so the pass
-// first turns the fragment's cross-shaped read region into shadow-test bits:
-//   row words    rows j0-r-1 .. j0+r+1, columns i0-R .. i0+R (bit p <-> i0-R+p)
-//   column words columns i0-r-1 .. i0+r+1, rows j0-R .. j0+R (bit q <-> j0-R+q)
-// with R = r + MAXDIST, so a word holds a whole line a term's traversal can
-// reach (2R+1 <= 63 bits).  A term's discontinuity mask is then a few shifts
-// and XORs (Eq. 2-3); a term without a discontinuity contributes its test
-// result, so those are counted with one popcount per column; and each bounded
-// traversal of Listing 3 becomes one count of trailing (or leading) ones on
-// "same test AND shares a discontinuity direction" bits (Sec. 3.1.3).  Only
-// terms with a discontinuity run the normalization (Eq. 5) and Listing 5.
+// first turns the fragment's (2r+3)^2 neighbourhood into shadow-test bits, one
+// 64-bit word per column (bit q <-> row j0-r-1+q).  A term's discontinuity
+// mask (Eq. 2-3) is then a few shifts and XORs, and the terms without a
+// discontinuity contribute their test result, so a column's worth of them is
+// one popcount.  Only the terms with a discontinuity need traversals
+// (Listing 3), normalization (Eq. 5) and Listing 5; their number varies
+// wildly between fragments, so each column's such terms are compacted over
+// the workgroup into an LDS list and evaluated one lane per term, keeping
+// every lane busy instead of holding a wave for its busiest fragment.  The
+// traversals read the two staged bands directly, the first two steps of all
+// four at once.
 //
 // The sum is kept in binary64 (exact for these terms in practice) and divided
 // by (2r+1)^2 once, so the result is the box average rounded to binary32 once.
@@ -27,10 +28,11 @@
 
 namespace rbsm {
 
-constexpr int kRpcfT = 128;        // threads per workgroup, one fragment each
-constexpr int kRpcfMaxReach = 31;  // largest r + MAXDIST whose lines fit one 64-bit word
+constexpr int kRpcfT = 128;    // threads per workgroup, one fragment each
+constexpr int kRpcfMaxR = 30;  // largest r whose 2r+3 rows fit one 64-bit column word
+constexpr int kRpcfEnt = 512;  // terms with a discontinuity evaluated per round
 
-// Any reach: one lane per fragment, every term evaluated from global memory
+// Any radius: one lane per fragment, every term evaluated from global memory
 // in the same a-major order, binary64 sum.
 __global__ __launch_bounds__(256) void rpcf_naive_kernel(MapView m, const float *__restrict__ frags, int64_t n,
                                                          float bias, int maxd, int r, float *__restrict__ out) {
@@ -46,9 +48,9 @@ __global__ __launch_bounds__(256) void rpcf_naive_kernel(MapView m, const float 
 }
 
 // Shadow-test bit of texel depth t for depth zb (Eq. 1): the sign bit of
-// t - zb.  For finite operands the difference is negative exactly when
-// zb > t, except for t = -0, zb = +0 (difference -0, test lit); callers pass
-// t + 0.0f, which turns -0 into +0.
+// t - zb.  The difference is negative exactly when zb > t, except for
+// t = -0, zb = +0 (difference -0, test lit) and for NaN; callers pass
+// canon(t), which turns -0 into +0 and NaN (lit at every depth) into +inf.
 __device__ __forceinline__ uint32_t push_bit(uint32_t w, float t, float zb) {
     return __builtin_amdgcn_alignbit(w, __float_as_uint(t - zb), 31);  // (w << 1) | sign
 }
@@ -79,88 +81,61 @@ __device__ __forceinline__ uint64_t shadow_bits(Rd rd, int nb, float zb) {
     return nb >= 64 ? all : all & ((1ull << nb) - 1ull);
 }
 
-// Bounded traversal towards increasing bit index from bit c.  `go` has a 1
-// where a step may continue (same test as the term and a shared
-// discontinuity direction), `same` where the test equals the term's.  The walk
-// stops at the first k >= 1 whose bit is 0 in `go`: an end (+k) when that
-// texel's test differs, else -k; -(maxd + 1) when it runs out.  Needs
-// c + maxd <= 63.
-__device__ __forceinline__ int walk_up_bits(uint64_t go, uint64_t same, int c, int maxd) {
-    const int k = __builtin_ctzll(~(go >> (c + 1))) + 1;
-    if (k > maxd) return -(maxd + 1);
-    return ((same >> (c + k)) & 1ull) ? -k : k;
-}
+__device__ __forceinline__ float canon(float t) { return t != t ? __builtin_inff() : t + 0.0f; }
 
-// The same towards decreasing bit index; needs 1 <= c and c - maxd >= 0.
-__device__ __forceinline__ int walk_down_bits(uint64_t go, uint64_t same, int c, int maxd) {
-    const int k = __builtin_clzll(~(go << (64 - c))) + 1;
-    if (k > maxd) return -(maxd + 1);
-    return ((same >> (c - k)) & 1ull) ? -k : k;
-}
+typedef __attribute__((address_space(3))) const char lds_byte;
 
-// One fragment's RPCF value from its row words (in LDS, word k of this lane
-// at rows[k * kRpcfT]) and column words built one column ahead by col(i).
-template <class ColFn>
-__device__ __forceinline__ float rpcf_terms(const uint64_t *rows, ColFn col, const Addr &A, int r, int maxd) {
-    const int R = r + maxd;
-    const uint64_t range = ((1ull << (2 * r + 1)) - 1ull) << (R - r);
-    double acc = 0.0;
-    uint64_t cm = col(A.i0 - r - 1), c0 = col(A.i0 - r);
-    for (int a = -r; a <= r; ++a) {
-        const uint64_t cp = col(A.i0 + a + 1);
-        const uint64_t Lc = c0 ^ cm, Rc = c0 ^ cp;
-        const uint64_t Tc = c0 ^ (c0 >> 1), Bc = c0 ^ (c0 << 1);
-        uint64_t edge = (Lc | Rc | Tc | Bc) & range;
-        // terms without a discontinuity: their own test (lit = 1)
-        acc += (double)__builtin_popcountll(~edge & ~c0 & range);
-        while (edge) {
-            const int q = __builtin_ctzll(edge);
-            edge &= edge - 1ull;
-            const bool s = ((c0 >> q) & 1ull) == 0ull;  // lit
-            const bool bl = (Lc >> q) & 1ull, br = (Rc >> q) & 1ull;
-            const bool bt = (Tc >> q) & 1ull, bb = (Bc >> q) & 1ull;
-            // vertical traversals along the column word
-            const uint64_t same_c = s ? ~c0 : c0;
-            const uint64_t go_c = same_c & ((bl ? Lc : 0ull) | (br ? Rc : 0ull));
-            const int rt = walk_up_bits(go_c, same_c, q, maxd);
-            const int rb = walk_down_bits(go_c, same_c, q, maxd);
-            // horizontal traversals along the term's row word
-            const int kk = q - R + r + 1;
-            const uint64_t h0 = rows[kk * kRpcfT];
-            const uint64_t hp = rows[(kk + 1) * kRpcfT];
-            const uint64_t hm = rows[(kk - 1) * kRpcfT];
-            const int p = R + a;
-            const uint64_t same_r = s ? ~h0 : h0;
-            const uint64_t go_r = same_r & ((bt ? (h0 ^ hp) : 0ull) | (bb ? (h0 ^ hm) : 0ull));
-            const int rr = walk_up_bits(go_r, same_r, p, maxd);
-            const int rl = walk_down_bits(go_r, same_r, p, maxd);
-            const Axis axx = normalize_axis(rl, rr, A.fx);
-            const Axis axy = normalize_axis(rb, rt, A.fy);
-            acc += (double)vis_rsmss(s, axx, axy);
-        }
-        cm = c0;
-        c0 = cp;
+// Three texel lines of a staged band, read at one offset: the line a
+// traversal moves along and its two side lines.
+struct BandWalkReader {
+    lds_byte *c, *a, *b;
+    __device__ __forceinline__ void operator()(int p, float &tc, float &ta, float &tb) const {
+        const unsigned x = 4u * (unsigned)p;
+        tc = *(const lds_float *)(c + x);
+        ta = *(const lds_float *)(a + x);
+        tb = *(const lds_float *)(b + x);
     }
-    return (float)(acc / (double)((2 * r + 1) * (2 * r + 1)));
+};
+
+// The first two steps of a traversal (Listing 3) from a staged band, with no
+// branches so that the reads of all four traversals of a term can be in
+// flight together: +k / -k for the first stopping step, 0 if neither stops.
+__device__ __forceinline__ int first_steps(const BandWalkReader &br, int p0, int d, int maxd, float zb, bool s,
+                                           bool chk_a, bool chk_b) {
+    float c1, a1, b1, c2, a2, b2;
+    br(p0 + d, c1, a1, b1);
+    br(p0 + (maxd >= 2 ? 2 * d : d), c2, a2, b2);
+    const bool end1 = (zb > c1) == s, end2 = (zb > c2) == s;
+    const bool share1 = (chk_a & ((zb > a1) == s)) | (chk_b & ((zb > b1) == s));
+    const bool share2 = (chk_a & ((zb > a2) == s)) | (chk_b & ((zb > b2) == s));
+    const int at2 = maxd >= 2 ? (end2 ? 2 : (share2 ? 0 : -2)) : 0;
+    return end1 ? 1 : (share1 ? at2 : -1);
 }
 
 // One workgroup per TW x (kRpcfT / TW) pixel tile of a row-major image of
-// width vw (flat: vw = n, TW = kRpcfT).  When both fit in `cap` texels, the
-// two bands the tile's words read are staged in LDS with clamped
-// coordinates, -0 stored as +0: the fragments' texel box grown by R
-// horizontally and r+1 vertically (row words), and grown by r+1 horizontally
-// and R vertically, stored transposed (column words), each with up to 7 more
-// texels along its lines for the 8-texel read chunks.  Every word is then
-// built from contiguous LDS reads.  Otherwise the words are built from global
-// memory.  Requires r >= 1, r + maxd <= kRpcfMaxReach.
+// width vw (flat: vw = n, TW = kRpcfT).  With R = r + maxd, the texels every
+// word and traversal of the tile reads lie in two bands, staged in LDS (with
+// canon() applied) when both fit in `cap` texels:
+//   H: rows of the fragments' texel box grown by r+1, columns grown by R
+//      (row-major; horizontal traversals);
+//   V: columns grown by r+1, rows grown by R, stored transposed, each column
+//      contiguous (column words and vertical traversals).
+// Band coordinates are unclamped positions holding clamped texels, so no read
+// clamps.  Otherwise everything reads global memory.  Requires 1 <= r <=
+// kRpcfMaxR.
 template <int TW>
 __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__restrict__ frags, int64_t n,
                                                       int64_t vw, int64_t tiles_x, float bias, int maxd, int r,
                                                       int cap, float *__restrict__ out) {
-    extern __shared__ uint64_t s_rpcf[];  // row words [(2r+3)][kRpcfT], then the staged bands
+    extern __shared__ float s_band[];
     __shared__ int s_red[kRpcfT / 64][4];
+    __shared__ int s_wtot[2][kRpcfT / 64];
+    __shared__ int s_fi[kRpcfT], s_fj[kRpcfT];
+    __shared__ float s_ffx[kRpcfT], s_ffy[kRpcfT], s_fzb[kRpcfT];
+    __shared__ uint32_t s_ent[kRpcfEnt];  // lane | q << 7 | lit << 13 | mask << 14
+    __shared__ float s_val[kRpcfEnt];
     constexpr int TH = kRpcfT / TW;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
     const int64_t tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
     const int64_t px = txi * TW + (t % TW), py = tyi * TH + (t / TW);
@@ -179,12 +154,17 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
         b2 = min(b2, __shfl_xor(b2, o));
         b3 = min(b3, __shfl_xor(b3, o));
     }
-    if ((t & 63) == 0) {
-        s_red[t >> 6][0] = b0;
-        s_red[t >> 6][1] = b1;
-        s_red[t >> 6][2] = b2;
-        s_red[t >> 6][3] = b3;
+    if (lane == 0) {
+        s_red[wave][0] = b0;
+        s_red[wave][1] = b1;
+        s_red[wave][2] = b2;
+        s_red[wave][3] = b3;
     }
+    s_fi[t] = A.i0;
+    s_fj[t] = A.j0;
+    s_ffx[t] = A.fx;
+    s_ffy[t] = A.fy;
+    s_fzb[t] = A.zb;
     __syncthreads();
     for (int w = 0; w < kRpcfT / 64; ++w) {
         b0 = min(b0, s_red[w][0]);
@@ -193,27 +173,23 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
         b3 = min(b3, s_red[w][3]);
     }
     if (b0 == INT32_MAX) return;  // no fragment in this tile (uniform)
-    const int nb = 2 * R + 1, pad = ((nb + 7) & ~7) - nb;
+    const int nbc = 2 * r + 3;    // bits of a column word
     const int fw = (-b1) - b0, fh = (-b3) - b2;  // texel box extent - 1
-    // horizontal band (row words), row-major: rows b2-r-1 .. , columns b0-R ..
     const int hx = b0 - R, hy = b2 - r - 1;
-    const int hw = fw + nb + pad, hh = fh + 2 * r + 3;
-    // vertical band (column words), stored column by column: columns b0-r-1 ..,
-    // rows b2-R .. ; an odd column length keeps the transposing stores
-    // conflict-free
+    const int hw = fw + 2 * R + 1, hh = fh + 2 * r + 3;
+    // column words read 8 texels at a time: up to 7 more rows; an odd column
+    // length keeps the transposing stores conflict-free
     const int vx = b0 - r - 1, vy = b2 - R;
-    const int vw_ = fw + 2 * r + 3, vh = (fh + nb + pad) | 1;
-    const bool staged = (int64_t)hw * hh + (int64_t)vw_ * vh <= cap;
-    uint64_t *rows = s_rpcf + t;
-    float *hb = reinterpret_cast<float *>(s_rpcf + (2 * r + 3) * kRpcfT);
-    float *vb = hb + (staged ? hw * hh : 0);
+    const int vwd = fw + 2 * r + 3, vh = (fh + 2 * R + 1 + 7) | 1;
+    const bool staged = (int64_t)hw * hh + (int64_t)vwd * vh <= cap;
+    float *hb = s_band, *vb = s_band + (staged ? hw * hh : 0);
     if (staged) {
         {
             const int area = hw * hh;
             int y = t / hw, x = t % hw;
             const int dy = kRpcfT / hw, dx = kRpcfT % hw;
             for (int idx = t; idx < area; idx += kRpcfT) {
-                hb[idx] = texel(m, hx + x, hy + y) + 0.0f;
+                hb[idx] = canon(texel(m, hx + x, hy + y));
                 y += dy;
                 x += dx;
                 if (x >= hw) {
@@ -224,75 +200,155 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
         }
         {
             // read row by row (coalesced), store transposed
-            const int area = vw_ * vh;
-            int y = t / vw_, x = t % vw_;
-            const int dy = kRpcfT / vw_, dx = kRpcfT % vw_;
+            const int area = vwd * vh;
+            int y = t / vwd, x = t % vwd;
+            const int dy = kRpcfT / vwd, dx = kRpcfT % vwd;
             for (int idx = t; idx < area; idx += kRpcfT) {
-                vb[x * vh + y] = texel(m, vx + x, vy + y) + 0.0f;
+                vb[x * vh + y] = canon(texel(m, vx + x, vy + y));
                 y += dy;
                 x += dx;
-                if (x >= vw_) {
-                    x -= vw_;
+                if (x >= vwd) {
+                    x -= vwd;
                     ++y;
                 }
             }
         }
     }
     __syncthreads();
-    if (!valid) return;
+    const lds_float *hbl = (const lds_float *)hb, *vbl = (const lds_float *)vb;
 
-    float res;
-    if (staged) {
-        const float *row0 = hb + (A.j0 - r - 1 - hy) * hw + (A.i0 - R - hx);
-        for (int kk = 0; kk < 2 * r + 3; ++kk) {
-            const float *line = row0 + kk * hw;
-            rows[kk * kRpcfT] = shadow_bits([&](int p) { return line[p]; }, nb, A.zb);
+    // shadow-test bits of column i, rows j0-r-1 .. j0+r+1
+    auto colword = [&](int i) -> uint64_t {
+        if (!valid) return 0ull;
+        if (staged) {
+            const lds_float *line = vbl + (i - vx) * vh + (A.j0 - r - 1 - vy);
+            return shadow_bits([&](int q) { return line[q]; }, nbc, A.zb);
         }
-        const int col0 = (A.j0 - R - vy) - vx * vh;
-        res = rpcf_terms(
-            rows,
-            [&](int i) {
-                const float *line = vb + (col0 + i * vh);
-                return shadow_bits([&](int q) { return line[q]; }, nb, A.zb);
-            },
-            A, r, maxd);
-    } else {
-        for (int kk = 0; kk < 2 * r + 3; ++kk) {
-            const int j = A.j0 - r - 1 + kk, i = A.i0 - R;
-            rows[kk * kRpcfT] = shadow_bits([&](int p) { return texel(m, i + p, j) + 0.0f; }, nb, A.zb);
+        const int j = A.j0 - r - 1;
+        return shadow_bits([&](int q) { return canon(texel(m, i, j + q)); }, nbc, A.zb);
+    };
+
+    const uint64_t range = ((1ull << (2 * r + 1)) - 1ull) << 1;  // rows j0-r .. j0+r
+    double acc = 0.0;
+    uint64_t cm = colword(A.i0 - r - 1), c0 = colword(A.i0 - r);
+    for (int a = -r; a <= r; ++a) {
+        const uint64_t cp = colword(A.i0 + a + 1);
+        const uint64_t Lc = c0 ^ cm, Rc = c0 ^ cp;
+        const uint64_t Tc = c0 ^ (c0 >> 1), Bc = c0 ^ (c0 << 1);
+        const uint64_t edge = valid ? (Lc | Rc | Tc | Bc) & range : 0ull;
+        // terms without a discontinuity: their own test (lit = 1)
+        acc += (double)__builtin_popcountll(~edge & ~c0 & range);
+
+        // this column's terms with a discontinuity: offsets over the workgroup
+        const int ne = __builtin_popcountll(edge);
+        int inc = ne;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
         }
-        res = rpcf_terms(
-            rows,
-            [&](int i) {
-                const int j = A.j0 - R;
-                return shadow_bits([&](int q) { return texel(m, i, j + q) + 0.0f; }, nb, A.zb);
-            },
-            A, r, maxd);
+        const int par = (a + r) & 1;  // double buffer: no barrier between columns without such terms
+        if (lane == 63) s_wtot[par][wave] = inc;
+        __syncthreads();
+        int off = inc - ne, tot = 0;
+        for (int w = 0; w < kRpcfT / 64; ++w) {
+            const int x = s_wtot[par][w];
+            off += w < wave ? x : 0;
+            tot += x;
+        }
+        for (int w0 = 0; w0 < tot; w0 += kRpcfEnt) {  // uniform
+            const int cnt = min(kRpcfEnt, tot - w0);
+            // list this lane's terms that fall in [w0, w0 + cnt)
+            if (off < w0 + cnt && off + ne > w0) {
+                uint64_t bits = edge;
+                for (int e = off; bits; ++e) {
+                    const int q = __builtin_ctzll(bits);
+                    bits &= bits - 1ull;
+                    if (e < w0 || e >= w0 + cnt) continue;
+                    const uint32_t mk = (uint32_t)((Lc >> q) & 1ull) * BIT_L | (uint32_t)((Rc >> q) & 1ull) * BIT_R |
+                                        (uint32_t)((Tc >> q) & 1ull) * BIT_T | (uint32_t)((Bc >> q) & 1ull) * BIT_B;
+                    const uint32_t lit_ = ((c0 >> q) & 1ull) == 0ull ? 1u : 0u;
+                    s_ent[e - w0] = (uint32_t)t | (uint32_t)q << 7 | lit_ << 13 | mk << 14;
+                }
+            }
+            __syncthreads();
+            // one lane per term: its four traversals, normalization (Eq. 5) and Listing 5
+            for (int e = t; e < cnt; e += kRpcfT) {
+                const uint32_t en = s_ent[e];
+                const int L = en & 127, q = (en >> 7) & 63;
+                const bool s = (en >> 13) & 1u;
+                const unsigned mk = en >> 14;
+                const int i = s_fi[L] + a, j = s_fj[L] - r - 1 + q;
+                const float zb = s_fzb[L];
+                int rd[4];  // left, right, top, bottom
+                if (staged) {
+                    // H: rows j, j+1 (top), j-1 (bottom) along columns;
+                    // V: columns i, i-1 (left), i+1 (right) along rows
+                    const lds_float *ph = hbl + (j - hy) * hw, *pv = vbl + (i - vx) * vh;
+                    BandWalkReader bh, bv;
+                    bh.c = (lds_byte *)ph;
+                    bh.a = (lds_byte *)(ph + hw);
+                    bh.b = (lds_byte *)(ph - hw);
+                    bv.c = (lds_byte *)pv;
+                    bv.a = (lds_byte *)(pv - vh);
+                    bv.b = (lds_byte *)(pv + vh);
+                    const int ph0 = i - hx, pv0 = j - vy;
+                    const bool ht = (mk & BIT_T) != 0, hbt = (mk & BIT_B) != 0;
+                    const bool vl = (mk & BIT_L) != 0, vr = (mk & BIT_R) != 0;
+                    rd[0] = first_steps(bh, ph0, -1, maxd, zb, s, ht, hbt);
+                    rd[1] = first_steps(bh, ph0, 1, maxd, zb, s, ht, hbt);
+                    rd[2] = first_steps(bv, pv0, 1, maxd, zb, s, vl, vr);
+                    rd[3] = first_steps(bv, pv0, -1, maxd, zb, s, vl, vr);
+                    // the few that run on
+                    for (int dir = 0; dir < 4; ++dir) {
+                        if (rd[dir] != 0) continue;
+                        const bool horiz = dir < 2;
+                        const int d = dir == 0 || dir == 3 ? -1 : 1;
+                        int x = 0;
+                        if (maxd > 2)
+                            x = walk_range<4>(horiz ? bh : bv, 3, maxd, horiz ? ph0 : pv0, d, INT32_MAX / 4, zb, s,
+                                              horiz ? ht : vl, horiz ? hbt : vr);
+                        rd[dir] = x != 0 ? x : -(maxd + 1);
+                    }
+                } else {
+                    rd[0] = walk_dir(m, i, j, zb, s, mk, maxd, -1, 0);
+                    rd[1] = walk_dir(m, i, j, zb, s, mk, maxd, 1, 0);
+                    rd[2] = walk_dir(m, i, j, zb, s, mk, maxd, 0, 1);
+                    rd[3] = walk_dir(m, i, j, zb, s, mk, maxd, 0, -1);
+                }
+                const Axis axx = normalize_axis(rd[0], rd[1], s_ffx[L]);
+                const Axis axy = normalize_axis(rd[3], rd[2], s_ffy[L]);
+                s_val[e] = vis_rsmss(s, axx, axy);
+            }
+            __syncthreads();
+            // each fragment adds its own terms, in list order
+            const int e_lo = max(off, w0), e_hi = min(off + ne, w0 + cnt);
+            for (int e = e_lo; e < e_hi; ++e) acc += (double)s_val[e - w0];
+        }
+        cm = c0;
+        c0 = cp;
     }
-    out[k] = res;
+    if (valid) out[k] = (float)(acc / (double)((2 * r + 1) * (2 * r + 1)));
 }
 
 // LDS texels for the staged bands of an RPCF workgroup: enough for a tile
-// whose texel footprint spans up to 13 x 17 texels, within 64 KiB in all.
+// whose texel footprint spans up to 13 x 17 texels, within 64 KiB with the
+// kernel's static LDS.
 inline int rpcf_cap(int r, int maxd) {
     const int R = r + maxd;
-    const int words = (2 * r + 3) * kRpcfT * 8;
-    const int want = (12 + 2 * R + 8) * (16 + 2 * r + 3) + (12 + 2 * r + 3) * (16 + 2 * R + 9);
-    const int room = (65536 - words - 256) / 4;
+    const int want = (12 + 2 * R + 1) * (16 + 2 * r + 3) + (12 + 2 * r + 3) * ((16 + 2 * R + 1 + 7) | 1);
+    const int room = (65536 - 10240) / 4;
     return want < room ? want : room;
 }
 
-inline size_t rpcf_lds_bytes(int r, int cap) { return (size_t)(2 * r + 3) * kRpcfT * 8 + (size_t)cap * 4; }
-
 inline void launch_rpcf(const MapView &mv, const float *frags, int64_t n, int64_t view_width, float bias, int maxd,
                         int r, float *out, hipStream_t stream) {
-    if (r + maxd > kRpcfMaxReach) {
+    if (r > kRpcfMaxR) {
         hipLaunchKernelGGL(rpcf_naive_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, mv, frags,
                            n, bias, maxd, r, out);
         return;
     }
     const int cap = rpcf_cap(r, maxd);
-    const size_t lds = rpcf_lds_bytes(r, cap);
+    const size_t lds = (size_t)cap * 4;
     if (view_width > 0) {
         constexpr int TW = 16, TH = kRpcfT / TW;
         const int64_t rows = (n + view_width - 1) / view_width;
