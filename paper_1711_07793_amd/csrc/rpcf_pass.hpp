@@ -29,6 +29,7 @@
 namespace rbsm {
 
 constexpr int kRpcfT = 128;    // threads per workgroup, one fragment each
+constexpr int kRpcfLaneBits = kRpcfT > 128 ? 8 : 7;  // lane field of a listed term
 constexpr int kRpcfMaxR = 30;  // largest r whose 2r+3 rows fit one 64-bit column word
 constexpr int kRpcfEnt = 512;  // terms with a discontinuity evaluated per round
 
@@ -132,9 +133,9 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     __shared__ int s_wtot[2][kRpcfT / 64];
     __shared__ int s_fi[kRpcfT], s_fj[kRpcfT];
     __shared__ float s_ffx[kRpcfT], s_ffy[kRpcfT], s_fzb[kRpcfT];
-    __shared__ uint32_t s_ent[kRpcfEnt];  // lane | q << 7 | lit << 13 | mask << 14
+    __shared__ uint32_t s_ent[kRpcfEnt];  // lane | q << LB | lit << (LB + 6) | mask << (LB + 7)
     __shared__ float s_val[kRpcfEnt];
-    constexpr int TH = kRpcfT / TW;
+    constexpr int TH = kRpcfT / TW, LB = kRpcfLaneBits;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
     const int64_t tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
@@ -267,16 +268,16 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
                     const uint32_t mk = (uint32_t)((Lc >> q) & 1ull) * BIT_L | (uint32_t)((Rc >> q) & 1ull) * BIT_R |
                                         (uint32_t)((Tc >> q) & 1ull) * BIT_T | (uint32_t)((Bc >> q) & 1ull) * BIT_B;
                     const uint32_t lit_ = ((c0 >> q) & 1ull) == 0ull ? 1u : 0u;
-                    s_ent[e - w0] = (uint32_t)t | (uint32_t)q << 7 | lit_ << 13 | mk << 14;
+                    s_ent[e - w0] = (uint32_t)t | (uint32_t)q << LB | lit_ << (LB + 6) | mk << (LB + 7);
                 }
             }
             __syncthreads();
             // one lane per term: its four traversals, normalization (Eq. 5) and Listing 5
             for (int e = t; e < cnt; e += kRpcfT) {
                 const uint32_t en = s_ent[e];
-                const int L = en & 127, q = (en >> 7) & 63;
-                const bool s = (en >> 13) & 1u;
-                const unsigned mk = en >> 14;
+                const int L = en & ((1u << LB) - 1u), q = (en >> LB) & 63;
+                const bool s = (en >> (LB + 6)) & 1u;
+                const unsigned mk = en >> (LB + 7);
                 const int i = s_fi[L] + a, j = s_fj[L] - r - 1 + q;
                 const float zb = s_fzb[L];
                 int rd[4];  // left, right, top, bottom
