@@ -107,10 +107,10 @@ __global__ __launch_bounds__(kCompT) void composite_batch_kernel(const CompArgs 
     composite_range(a.jobs[j], (g - a.first[j]) * (kCompT * kCompF) + threadIdx.x);
 }
 
-// The batched tile pass of a scheduling step, one launch per mode and chunk of
-// jobs: each tile runs the code of the single-view pass, with its occupancy
-// (64 VGPRs, 8 workgroups per CU at the default LDS capacity).
-template <bool HARD, int TW>
+// The batched tile pass of a scheduling step, one launch per chunk of jobs of
+// either mode: each tile runs the steps of the single-view pass, with its
+// occupancy (64 VGPRs, 8 workgroups per CU at the default LDS capacity).
+template <int TW>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void serve_kernel(const ServeArgs a,
                                                                                               int apron, int cap) {
     extern __shared__ float s_tex[];
@@ -118,8 +118,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const int j = find_job(a.first, a.n_jobs, g);
     const JobDev &J = a.jobs[j];
-    process_tile<HARD, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                           g - a.first[j], sh, s_tex);
+    process_tile<2, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
+                        g - a.first[j], sh, s_tex, J.mode == 0);
 }
 
 }  // namespace rbsm
@@ -230,7 +230,7 @@ bool rbsm_engine::step_launch() {
     if (s < 0 || admitted.empty()) return false;
     Slot &S = slots[s];
     std::vector<EngineReq *> batch;
-    std::vector<std::pair<EngineReq *, int>> rpcf_jobs, tile_jobs[2];  // [0] hard, [1] RSMSS
+    std::vector<std::pair<EngineReq *, int>> rpcf_jobs, tile_jobs;  // (request, light)
     std::vector<rbsm::CompJob> comps;
     int n_jobs = 0;
     size_t taken = 0;
@@ -241,7 +241,7 @@ bool rbsm_engine::step_launch() {
         n_jobs += q.n_lights;
         for (int l = 0; l < q.n_lights; ++l) {
             if (q.lights[l].kernel_radius > 0) rpcf_jobs.push_back({R, l});
-            else tile_jobs[q.lights[l].mode].push_back({R, l});
+            else tile_jobs.push_back({R, l});
         }
         if (R->d_comp && q.n > 0) {
             rbsm::CompJob C{};
@@ -262,10 +262,10 @@ bool rbsm_engine::step_launch() {
 
     hipError_t e = hipEventRecord(S.compute_start, s_compute);
     const size_t lds = (size_t)kDefaultTile.cap * sizeof(float);
-    // tile jobs: per mode, in chunks that fit the kernel arguments
-    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
-        const auto &list = tile_jobs[g];
-        for (size_t c0 = 0; c0 < list.size(); c0 += rbsm::kArgJobs) {
+    // tile jobs of both modes, in chunks that fit the kernel arguments
+    {
+        const auto &list = tile_jobs;
+        for (size_t c0 = 0; c0 < list.size() && e == hipSuccess; c0 += rbsm::kArgJobs) {
             rbsm::ServeArgs A{};
             int64_t tiles = 0;
             for (size_t c = c0; c < list.size() && c < c0 + rbsm::kArgJobs; ++c) {
@@ -291,12 +291,8 @@ bool rbsm_engine::step_launch() {
                 tiles += lay.tiles;
             }
             if (tiles == 0) continue;
-            if (g == 0)
-                hipLaunchKernelGGL((rbsm::serve_kernel<true, kDefaultTile.tile_w>), dim3((unsigned)tiles), dim3(kT), lds, s_compute, A,
-                                   kDefaultTile.apron, kDefaultTile.cap);
-            else
-                hipLaunchKernelGGL((rbsm::serve_kernel<false, kDefaultTile.tile_w>), dim3((unsigned)tiles), dim3(kT), lds, s_compute,
-                                   A, kDefaultTile.apron, kDefaultTile.cap);
+            hipLaunchKernelGGL((rbsm::serve_kernel<kDefaultTile.tile_w>), dim3((unsigned)tiles), dim3(kT), lds,
+                               s_compute, A, kDefaultTile.apron, kDefaultTile.cap);
         }
     }
     for (const auto &rj : rpcf_jobs) {

@@ -177,11 +177,14 @@ struct TileShared {
     int count, ncont;
 };
 
-template <bool HARD, int TW>
+// MODE: 1 hard pass, 0 RSMSS, 2 either, chosen per call by hard_rt (one code
+// path for workgroups of both modes in one launch).
+template <int MODE, int TW>
 __device__ __forceinline__ void process_tile(MapView m, const float *__restrict__ frags, int64_t n, int64_t vw,
                                              int64_t tiles_x, float bias, int maxd, int apron, int cap,
                                              int vec_ok, void *__restrict__ out_v, int64_t tile_id,
-                                             TileShared &sh, float *s_tex) {
+                                             TileShared &sh, float *s_tex, bool hard_rt = false) {
+    const bool HARD = MODE == 2 ? hard_rt : MODE == 1;
     constexpr int TH = kTileF / TW;
     constexpr int LPR = TW / kF;
     auto &s_box = sh.box;
@@ -525,22 +528,19 @@ struct JobDev {
 };
 
 // Batched pass: one workgroup per tile of any job; block_job maps the
-// (XCD-ordered) workgroup index to its job.  Each tile runs exactly the code
-// of the single-view pass, so every output is bitwise the same.
+// (XCD-ordered) workgroup index to its job.  Each tile runs the steps of the
+// single-view pass, so every output is bitwise the same; the mode is a
+// per-workgroup value, so one code path serves both and fits 64 VGPRs.
 template <int TW>
-__global__ __launch_bounds__(kT) void batch_kernel(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_kernel(const JobDev *__restrict__ jobs,
                                                    const uint16_t *__restrict__ block_job, int apron, int cap) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
     const int64_t g = xcd_block(blockIdx.x, gridDim.x);
     const JobDev J = jobs[block_job[g]];
     const int64_t tile = g - J.tile_base;
-    if (J.mode == 0)
-        process_tile<true, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                               tile, sh, s_tex);
-    else
-        process_tile<false, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                                tile, sh, s_tex);
+    process_tile<2, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out, tile, sh,
+                        s_tex, J.mode == 0);
 }
 
 // Launch configuration of the main pass (defaults of the plain entry points).
