@@ -4,8 +4,9 @@ Coverage is decided in binary64 on both sides and depths are binary32
 minima, so maps must be bit-equal: whole maps at sizes the oracle finishes
 quickly, sampled texels at full workload sizes, and the edge cases (tiny and
 padded maps, no primitives, primitives the tile lists cannot hold, primitives
-outside the map, malformed records).  End to end, a map rasterized on the
-device feeds the shadow pass to the same result as the oracle's map.
+outside the map, malformed records, equal and NaN depths).  End to end, a
+map rasterized on the device feeds the shadow pass to the same result as the
+oracle's map.
 """
 import numpy as np
 import pytest
@@ -83,9 +84,9 @@ def test_padded_tiny_and_empty(rb):
     assert np.all(o[:, 40:] == -7.0)
 
 
-def test_more_primitives_than_a_tile_lists(rb):
-    """3000 small triangles over one 64^2 map: every tile lists more than
-    its capacity and tests all primitives instead."""
+def test_thousands_of_overlapping_primitives(rb):
+    """3000 large triangles over one 64^2 map: each tile sees all of them;
+    those covering it whole fold into one depth, the rest are listed."""
     rng = np.random.default_rng(12)
     n = 3000
     p = np.zeros(n, oracle.PRIM_DTYPE)
@@ -100,6 +101,50 @@ def test_more_primitives_than_a_tile_lists(rb):
         p[k]["depth"] = rng.uniform(0.1, 0.8)
     rec = (0.9, 0.0, 0.0)
     assert np.array_equal(gpu_raster(rb, p, rec, 64, 64), oracle.raster(p, rec, 64, 64))
+
+
+def test_small_primitives_overflow_the_tile_list(rb):
+    """3000 small triangles inside one 32 x 32 tile: they only partly cover
+    it, so the tile lists more than its capacity and tests every primitive."""
+    rng = np.random.default_rng(13)
+    n = 3000
+    p = np.zeros(n, oracle.PRIM_DTYPE)
+    c = rng.uniform(0.05, 0.45, (n, 2))
+    for k in range(n):
+        ang = np.sort(rng.uniform(0, 2 * np.pi, 3))
+        r = rng.uniform(0.005, 0.03)
+        p[k]["kind"], p[k]["nv"] = 0, 3
+        p[k]["x"][:3] = c[k, 0] + r * np.cos(ang)
+        p[k]["y"][:3] = c[k, 1] + r * np.sin(ang)
+        p[k]["depth"] = rng.uniform(0.1, 0.8)
+    rec = (0.9, 0.0, 0.0)
+    assert np.array_equal(gpu_raster(rb, p, rec, 64, 64), oracle.raster(p, rec, 64, 64))
+
+
+def test_equal_depths_take_the_lowest_index(rb):
+    """+0 and -0 compare equal: among equal depths the receiver plane wins,
+    then the primitive of lowest index, in both orders; NaN depths never win.
+    Bits are compared, so the sign of a zero counts."""
+    def quad(x0, y0, x1, y1, z):
+        q = np.zeros(1, oracle.PRIM_DTYPE)
+        q["kind"], q["nv"] = 0, 4
+        q["x"][0, :4] = [x0, x1, x1, x0]
+        q["y"][0, :4] = [y0, y0, y1, y1]
+        q["depth"] = z
+        return q
+    big = (-0.5, -0.5, 1.5, 1.5)
+    cases = [
+        np.concatenate([quad(*big, 0.0), quad(*big, -0.0)]),
+        np.concatenate([quad(*big, -0.0), quad(*big, 0.0)]),
+        np.concatenate([quad(0.1, 0.1, 0.7, 0.6, np.nan), quad(0.2, 0.3, 0.9, 0.8, 0.3),
+                        quad(0.0, 0.0, 0.5, 0.5, 0.3), quad(*big, np.nan)]),
+    ]
+    for rec in ((0.9, 0.0, 0.0), (0.0, 0.0, 0.0), (-0.0, 0.0, 0.0)):
+        for pr in cases:
+            for (W, H) in ((64, 64), (45, 70)):
+                got = gpu_raster(rb, pr, rec, W, H)
+                want = oracle.raster(pr, rec, W, H)
+                assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (rec, W, H, pr["depth"])
 
 
 def test_outside_and_malformed_primitives(rb):
