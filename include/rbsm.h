@@ -201,7 +201,9 @@ void rbsm_plan_destroy(rbsm_plan *plan);
  * Texel (i, j) samples its centre u = (i + 0.5) / width, v = (j + 0.5) /
  * height and stores the nearest surface there: the minimum of the receiver
  * plane r0 + ru (u - 0.5) + rv (v - 0.5) (evaluated in binary64, rounded to
- * binary32) and the depth of every primitive covering the centre.  A convex
+ * binary32) and the depth of every primitive covering the centre; among equal
+ * depths (+0 and -0 compare equal; a NaN depth never wins) the plane, then the
+ * primitive of lowest index, is kept.  A convex
  * polygon (vertices counter-clockwise in (u, v)) covers a point when no edge
  * function (b - a) x (p - a) is negative and each zero lies on an edge that
  * runs downwards or horizontally to the left (top-left tie rule); a slab
