@@ -106,29 +106,6 @@ __device__ __forceinline__ int walk_dir(const MapView &m, int i0, int j0, float 
     return -(maxd + 1);
 }
 
-// The fragment's row triple (i0-1, i0, i0+1) of row j, clamped to the map,
-// read with one 12-byte load when the map is at least 3 texels wide.
-__device__ __forceinline__ void row3(const MapView &m, int i0, int j, float &L, float &C, float &R) {
-    const int jj = min(max(j, 0), m.H - 1);
-    const float *row = m.t + (int64_t)jj * m.pitch;
-    const int il = min(max(i0 - 1, 0), m.W - 1);
-    const int ic = min(max(i0, 0), m.W - 1);
-    const int ir = min(max(i0 + 1, 0), m.W - 1);
-    if (m.W >= 3) {
-        struct Tri { float x, y, z; } r;
-        const int c0 = min(max(i0 - 1, 0), m.W - 3);
-        __builtin_memcpy(&r, row + c0, sizeof(r));
-        const int ol = il - c0, oc = ic - c0, orr = ir - c0;
-        L = ol == 0 ? r.x : (ol == 1 ? r.y : r.z);
-        C = oc == 0 ? r.x : (oc == 1 ? r.y : r.z);
-        R = orr == 0 ? r.x : (orr == 1 ? r.y : r.z);
-    } else {
-        L = row[il];
-        C = row[ic];
-        R = row[ir];
-    }
-}
-
 // One axis of the normalized discontinuity space (Eq. 5): the code counts the
 // walks that found an end (2 -> 1, 1 -> 0, 0 -> -1); with exactly one end the
 // coordinate is the fragment's distance to the end texel's boundary over the

@@ -77,49 +77,10 @@ __device__ __forceinline__ void stage_rect(const MapView &m, float *dst, int x0,
     }
 }
 
-// Is texel (i, j), clamped, in the staged box?  Returns its LDS index or -1.
-__device__ __forceinline__ int staged_index(const MapView &m, const Staged &st, int i, int j) {
-    i = min(max(i, 0), m.W - 1);
-    j = min(max(j, 0), m.H - 1);
-    if (!st.on || i < st.bx0 || i > st.bx1 || j < st.by0 || j > st.by1) return -1;
-    return (j - st.by0) * st.bw + (i - st.bx0);
-}
-
-// Clamp-to-edge read: LDS inside the staged box, global memory outside.
-__device__ __forceinline__ float fetch(const MapView &m, const Staged &st, int i, int j) {
-    const int li = staged_index(m, st, i, j);
-    if (li >= 0) return st.lds[li];
-    i = min(max(i, 0), m.W - 1);
-    j = min(max(j, 0), m.H - 1);
-    return m.t[(int64_t)j * m.pitch + i];
-}
-
-// One workgroup owns a TW x (1024/TW) pixel tile of a row-major image of
-// width vw (flat mode: vw = n, TW = 1024); each thread owns 4 consecutive
-// pixels of one row (one 48-byte fragment load, one packed store).
-//  1. load fragments; the workgroup reduces the bounding box of their texels,
-//     grows it by `apron` texels and, when it holds at most `cap` texels,
-//     copies it into LDS with row-contiguous loads (else reads stay global);
-//  2. centre and neighbour tests; fragments without a discontinuity (and, in
-//     hard mode, shadowed ones) are final and stored at once;
-//  3. edge fragments are compacted with wave ballots into an LDS queue that
-//     keeps their texel, depth, sub-texel position, test and mask;
-//  4. tiles with edge fragments restage: a horizontal band (the box rows
-//     +-1, columns +-(MAXDIST+1)) and a vertical band (the box columns +-1,
-//     rows +-(MAXDIST+1)) hold every texel any traversal of the tile reads;
-//  5. one lane per (edge fragment, direction) walks in blocks of 8 steps,
-//     all reads of a block issued together, from the bands (from global
-//     memory when the bands exceed the LDS capacity);
-//  6. one lane per edge fragment normalizes, evaluates the visibility
-//     function and stores.
-// Staging, tile shape and queues only decide where texels are read from and
-// by which lane: every result equals the per-fragment listing.
-// Workgroup-shared state of one tile (the staged texels live in the dynamic
-// LDS array that follows it).
 // Bounded traversal (Listing 3) of one walk, a range of its steps at a time in
-// blocks of NB steps, every read of a block issued together.  The walk moves along one
-// coordinate p (clamped to [0, pmax]); the other coordinate is fixed for the
-// texel on the walk and for its two side neighbours (the texels of the
+// blocks of NB steps, every read of a block issued together.  The walk moves
+// along one coordinate p (clamped to [0, pmax]); the other coordinate is fixed
+// for the texel on the walk and for its two side neighbours (the texels of the
 // shared-discontinuity test), so a reader maps p to three texel values.
 // walk_range returns +k (the walk ends at step k) or -k (it leaves the
 // discontinuity at step k) for the first stopping step in [k0, k1], or 0.
@@ -166,6 +127,8 @@ __device__ __forceinline__ int walk_range(const Reader &rd3, int k0, int k1, int
     return 0;
 }
 
+// Workgroup-shared state of one tile (the staged texels live in the dynamic
+// LDS array that follows it).
 struct TileShared {
     int box[kT / 64][4];
     int16_t slot[kTileF];
@@ -177,6 +140,23 @@ struct TileShared {
     int count, ncont;
 };
 
+// One workgroup owns a TW x (1024/TW) pixel tile of a row-major image of
+// width vw (flat mode: vw = n, TW = 1024); each thread owns 4 consecutive
+// pixels of one row (one 48-byte fragment load, one packed store).
+//  1. load fragments; the workgroup reduces the bounding box of their texels,
+//     grows it by `apron` texels and, when it holds at most `cap` texels,
+//     copies it into LDS with row-contiguous loads (else reads stay global);
+//  2. centre and neighbour tests; fragments without a discontinuity (and, in
+//     hard mode, shadowed ones) are final and stored at once;
+//  3. edge fragments are compacted with wave ballots into an LDS queue that
+//     keeps their texel, depth, sub-texel position, test and mask;
+//  4. one lane per (edge fragment, direction) takes the walk's first
+//     kWalkFirst steps from global memory (L2); walks still running are
+//     queued again and continued in blocks of kWalkSteps steps;
+//  5. one lane per edge fragment normalizes, evaluates the visibility
+//     function and stores.
+// Staging, tile shape and queues only decide where texels are read from and
+// by which lane: every result equals the per-fragment listing.
 // MODE: 1 hard pass, 0 RSMSS, 2 either, chosen per call by hard_rt (one code
 // path for workgroups of both modes in one launch).
 template <int MODE, int TW>
