@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     __shared__ int s_wtot[2][kRpcfT / 64];
     __shared__ int s_fi[kRpcfT], s_fj[kRpcfT];
     __shared__ float s_ffx[kRpcfT], s_ffy[kRpcfT], s_fzb[kRpcfT];
-    __shared__ uint32_t s_ent[kRpcfEnt];  // lane | q << LB | lit << (LB + 6) | mask << (LB + 7)
+    __shared__ uint32_t s_ent[kRpcfEnt];  // lane | q << LB | lit << (LB+6) | mask << (LB+7) | column << (LB+11)
     __shared__ float s_val[kRpcfEnt];
     constexpr int TH = kRpcfT / TW, LB = kRpcfLaneBits;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -231,23 +231,28 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
 
     const uint64_t range = ((1ull << (2 * r + 1)) - 1ull) << 1;  // rows j0-r .. j0+r
     double acc = 0.0;
+    // two columns per round, a and a + 1: words cm (a-1), c0 (a), c1 (a+1), c2 (a+2)
     uint64_t cm = colword(A.i0 - r - 1), c0 = colword(A.i0 - r);
-    for (int a = -r; a <= r; ++a) {
-        const uint64_t cp = colword(A.i0 + a + 1);
-        const uint64_t Lc = c0 ^ cm, Rc = c0 ^ cp;
-        const uint64_t Tc = c0 ^ (c0 >> 1), Bc = c0 ^ (c0 << 1);
-        const uint64_t edge = valid ? (Lc | Rc | Tc | Bc) & range : 0ull;
+    for (int a = -r; a <= r; a += 2) {
+        const bool two = a + 1 <= r;  // uniform
+        const uint64_t c1 = colword(A.i0 + a + 1);
+        const uint64_t c2 = two ? colword(A.i0 + a + 2) : 0ull;
+        // discontinuity masks of column x (words w_-, w, w_+): L, R, T, B
+        const uint64_t e0 = valid ? ((c0 ^ cm) | (c0 ^ c1) | (c0 ^ (c0 >> 1)) | (c0 ^ (c0 << 1))) & range : 0ull;
+        const uint64_t e1 =
+            valid && two ? ((c1 ^ c0) | (c1 ^ c2) | (c1 ^ (c1 >> 1)) | (c1 ^ (c1 << 1))) & range : 0ull;
         // terms without a discontinuity: their own test (lit = 1)
-        acc += (double)__builtin_popcountll(~edge & ~c0 & range);
+        acc += (double)__builtin_popcountll(~e0 & ~c0 & range);
+        if (two) acc += (double)__builtin_popcountll(~e1 & ~c1 & range);
 
-        // this column's terms with a discontinuity: offsets over the workgroup
-        const int ne = __builtin_popcountll(edge);
+        // this round's terms with a discontinuity: offsets over the workgroup
+        const int n0 = __builtin_popcountll(e0), ne = n0 + __builtin_popcountll(e1);
         int inc = ne;
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(inc, o);
             if (lane >= o) inc += y;
         }
-        const int par = (a + r) & 1;  // double buffer: no barrier between columns without such terms
+        const int par = ((a + r) >> 1) & 1;  // double buffer: no barrier between rounds without such terms
         if (lane == 63) s_wtot[par][wave] = inc;
         __syncthreads();
         int off = inc - ne, tot = 0;
@@ -258,17 +263,24 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
         }
         for (int w0 = 0; w0 < tot; w0 += kRpcfEnt) {  // uniform
             const int cnt = min(kRpcfEnt, tot - w0);
-            // list this lane's terms that fall in [w0, w0 + cnt)
+            // list this lane's terms that fall in [w0, w0 + cnt): column a, then a + 1
             if (off < w0 + cnt && off + ne > w0) {
-                uint64_t bits = edge;
-                for (int e = off; bits; ++e) {
-                    const int q = __builtin_ctzll(bits);
-                    bits &= bits - 1ull;
-                    if (e < w0 || e >= w0 + cnt) continue;
-                    const uint32_t mk = (uint32_t)((Lc >> q) & 1ull) * BIT_L | (uint32_t)((Rc >> q) & 1ull) * BIT_R |
-                                        (uint32_t)((Tc >> q) & 1ull) * BIT_T | (uint32_t)((Bc >> q) & 1ull) * BIT_B;
-                    const uint32_t lit_ = ((c0 >> q) & 1ull) == 0ull ? 1u : 0u;
-                    s_ent[e - w0] = (uint32_t)t | (uint32_t)q << LB | lit_ << (LB + 6) | mk << (LB + 7);
+                int e = off;
+                for (int x = 0; x < 2; ++x) {
+                    const uint64_t wl = x ? c0 : cm, w = x ? c1 : c0, wr = x ? c2 : c1;
+                    uint64_t bits = x ? e1 : e0;
+                    for (; bits; ++e) {
+                        const int q = __builtin_ctzll(bits);
+                        bits &= bits - 1ull;
+                        if (e < w0 || e >= w0 + cnt) continue;
+                        const uint32_t mk = (uint32_t)(((w ^ wl) >> q) & 1ull) * BIT_L |
+                                            (uint32_t)(((w ^ wr) >> q) & 1ull) * BIT_R |
+                                            (uint32_t)(((w ^ (w >> 1)) >> q) & 1ull) * BIT_T |
+                                            (uint32_t)(((w ^ (w << 1)) >> q) & 1ull) * BIT_B;
+                        const uint32_t lit_ = ((w >> q) & 1ull) == 0ull ? 1u : 0u;
+                        s_ent[e - w0] = (uint32_t)t | (uint32_t)q << LB | lit_ << (LB + 6) | mk << (LB + 7) |
+                                        (uint32_t)x << (LB + 11);
+                    }
                 }
             }
             __syncthreads();
@@ -277,8 +289,8 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
                 const uint32_t en = s_ent[e];
                 const int L = en & ((1u << LB) - 1u), q = (en >> LB) & 63;
                 const bool s = (en >> (LB + 6)) & 1u;
-                const unsigned mk = en >> (LB + 7);
-                const int i = s_fi[L] + a, j = s_fj[L] - r - 1 + q;
+                const unsigned mk = (en >> (LB + 7)) & 15u;
+                const int i = s_fi[L] + a + (int)((en >> (LB + 11)) & 1u), j = s_fj[L] - r - 1 + q;
                 const float zb = s_fzb[L];
                 int rd[4];  // left, right, top, bottom
                 if (staged) {
@@ -325,8 +337,8 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
             const int e_lo = max(off, w0), e_hi = min(off + ne, w0 + cnt);
             for (int e = e_lo; e < e_hi; ++e) acc += (double)s_val[e - w0];
         }
-        cm = c0;
-        c0 = cp;
+        cm = c1;
+        c0 = c2;
     }
     if (valid) out[k] = (float)(acc / (double)((2 * r + 1) * (2 * r + 1)));
 }
