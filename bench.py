@@ -220,10 +220,22 @@ def batched_section(torch, rb, frames_timed: int = 20):
     plan.capture(s)
     graph = run(lambda: plan.launch(s), s.synchronize)
     plan.close()
+    # algorithmic bytes of one frame: 12 B per fragment in, the outputs, and
+    # 4 B per distinct texel each job reads (counted on the device)
+    frame_bytes = 0
+    for j in jobs:
+        n = j["frags"].numel() // 3
+        t = rb.rbsm_footprint(j["map"], j["frags"], j["params"], j["mode"])
+        frame_bytes += (12 + (1 if j["mode"] == 0 else 4)) * n + 4 * int(t.sum().item())
+        del t
+    for res in (plain, batched, graph):
+        res["achieved_GBps"] = frame_bytes * res["fragments_per_s"] / n_frag / 1e9
     return {
         "workload": "16 maps (cascades 8192^2..1024^2 + 12 spot maps 1024^2..4096^2), 8 views 720p..4K, "
                     f"{len(jobs)} jobs (cascades hard, spots RSMSS r=0)",
         "fragments_per_frame": n_frag,
+        "algorithmic_bytes_per_frame": frame_bytes,
+        "hbm_peak_GBps": 8000.0,
         "plain_per_view": plain,
         "batched": batched,
         "batched_graph": graph,
