@@ -212,6 +212,28 @@ def test_pitch_and_nonsquare_and_tiny_maps(rb):
         check_soft(m, f, dict(pd, kernel_radius=2), got_r)
 
 
+def test_nan_texels(rb):
+    """A NaN texel compares false, so it is lit for every fragment (fragments
+    themselves must be finite): both signs of NaN, every mode, staged and
+    global reads (view_width 0 and 97)."""
+    rng = np.random.default_rng(14)
+    W = 48
+    m = np.where(rng.random((W, W)) < 0.35, 0.5, 0.9).astype(np.float32)
+    nan_p = np.float32(np.nan)
+    nan_n = np.frombuffer(np.array([0xFFC00000], np.uint32).tobytes(), np.float32)[0]
+    m[rng.random((W, W)) < 0.05] = nan_p
+    m[rng.random((W, W)) < 0.05] = nan_n
+    f = _frags_for(W, W, 6000, seed=14, spill=0.05)
+    md, fd = dev(m), dev(f)
+    for vw in (0, 97):
+        p = dict(width=W, height=W, pitch=W, depth_bias=1e-4, max_dist=9, kernel_radius=0, view_width=vw)
+        check_hard(m, f, p, rb.rbsm_visibility(md, fd, p).cpu().numpy())
+        check_soft(m, f, p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
+        for r in (1, 3):
+            pr = dict(p, kernel_radius=r)
+            check_soft(m, f, pr, rb.rsmss_visibility(md, fd, pr).cpu().numpy())
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4099])
 def test_ragged_sizes(rb, n):
     c = synth.make_config(1, 1005, small=True)
