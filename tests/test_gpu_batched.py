@@ -143,3 +143,34 @@ def test_update_swaps_buffers_with_the_same_layout(rb, workload):
     bad = [dict(jobs2[0], frags=jobs2[0]["frags"][:10].contiguous(), out=jobs2[0]["out"][:10])] + jobs2[1:]
     with pytest.raises(rb.RbsmError):
         plan.update(bad)
+
+
+def test_full_size_workload_sampled_against_oracle(rb):
+    """The batched workload at full size (16 maps up to 8192^2, 8 views up to
+    4K, 66.5 M fragment evaluations) in the launch configuration the bench
+    times (autotuned): sampled fragments of every job against the oracle."""
+    w = synth.make_batched(4001)
+    maps, jobs = _device_jobs(rb, w, extra_flat=False)
+    plan = rb.Plan(jobs)
+    plan.autotune(reps=1)
+    plan.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4002)
+    for k, j in enumerate(jobs):
+        h = j["host"]
+        n = len(h["frags"])
+        idx = np.sort(rng.choice(n, min(n, 1500), replace=False))
+        got = j["out"].cpu().numpy()[idx]
+        f = np.ascontiguousarray(h["frags"][idx])
+        m = w["maps"][h["map"]]
+        p = dict(h["params"], pitch=m.shape[1])
+        if j["mode"] == 0:
+            want = oracle.rbsm_hard(m, f, p)
+            bad = np.nonzero(got != want)[0]
+            assert len(bad) <= max(0, int(1e-5 * len(want))), (k, len(bad))
+        else:
+            want = oracle.rsmss(m, f, p)
+            assert np.max(np.abs(got.astype(np.float64) - want)) <= 1e-5, k
+    plan.close()
+    del maps, jobs
+    torch.cuda.empty_cache()
