@@ -234,3 +234,52 @@ def test_poisson_arrivals_complete(rb, world):
     st = eng.stats()
     assert st["completed"] == len(world["reqs"]) and st["queued"] == 0 and st["inflight"] == 0
     eng.close()
+
+
+def test_full_size_requests_sampled_against_oracle(rb):
+    """Serving at full size: resident lights of 1024^2..8192^2 and views of
+    720p..4K, as the bench runs them (device destinations, a composite per
+    request); sampled fragments of every light and of the composite against
+    the oracle."""
+    sizes = [1024, 4096, 8192, 2048]
+    views = [(1280, 720), (1920, 1080), (3840, 2160)]
+    scenes = [synth.triangle_scene(7500 + li, S, S, 64) for li, S in enumerate(sizes)]
+    maps = [sc.raster() for sc in scenes]
+    eng = rb.Engine(4 << 30, 8)
+    ids = [eng.add_light(torch.from_numpy(m).cuda()) for m in maps]
+    rng = np.random.default_rng(7501)
+    reqs = [(0, [0, 2]), (1, [1, 3, 2]), (2, [2, 0]), (2, [3]), (1, [0, 1, 2, 3])]
+    for vi, ls in reqs:
+        w, h = views[vi]
+        n = w * h
+        host_frags = [scenes[li].camera_fragments(7600 + 10 * li + vi, w, h) for li in ls]
+        lights, outs = [], []
+        for k, li in enumerate(ls):
+            mode = li % 2
+            o = torch.empty(n, dtype=torch.uint8 if mode == 0 else torch.float32, device="cuda")
+            outs.append(o)
+            lights.append(dict(light=ids[li], mode=mode, frags=torch.from_numpy(host_frags[k]).cuda(),
+                               depth_bias=1e-4, max_dist=16, weight=float(np.float32(0.25 + 0.5 * k / len(ls))),
+                               out=o))
+        comp = torch.empty(n, dtype=torch.float32, device="cuda")
+        t = eng.submit(n, lights, view_width=w, composite=comp)
+        assert eng.wait(t, 60000) is not None
+        idx = np.sort(rng.choice(n, 1200, replace=False))
+        vis = []
+        for k, li in enumerate(ls):
+            m = maps[li]
+            f = np.ascontiguousarray(host_frags[k][idx])
+            p = dict(width=m.shape[1], height=m.shape[0], pitch=m.shape[1], depth_bias=1e-4, max_dist=16,
+                     kernel_radius=0)
+            got = outs[k].cpu().numpy()[idx]
+            if li % 2 == 0:
+                v = oracle.rbsm_hard(m, f, p)
+                assert np.array_equal(got, v), (vi, li)
+            else:
+                v = oracle.rsmss(m, f, p)
+                assert np.max(np.abs(got.astype(np.float64) - v)) <= SOFT_TOL, (vi, li)
+            vis.append(v)
+        wc = oracle.composite(vis, [L["weight"] for L in lights])
+        tol = SOFT_TOL * sum(L["weight"] for L in lights) + 1e-6
+        assert np.max(np.abs(comp.cpu().numpy()[idx].astype(np.float64) - wc)) <= tol, vi
+    eng.close()
