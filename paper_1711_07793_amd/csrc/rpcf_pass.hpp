@@ -10,8 +10,8 @@
 // discontinuity contribute their test result, so a column's worth of them is
 // one popcount.  Only the terms with a discontinuity need traversals
 // (Listing 3), normalization (Eq. 5) and Listing 5; their number varies
-// wildly between fragments, so each column's such terms are compacted over
-// the workgroup into an LDS list and evaluated one lane per term, keeping
+// wildly between fragments, so such terms of each pair of columns are compacted
+// over the workgroup into an LDS list and evaluated one lane per term, keeping
 // every lane busy instead of holding a wave for its busiest fragment.  The
 // traversals read the two staged bands directly, the first two steps of all
 // four at once.
