@@ -145,6 +145,32 @@ def test_update_swaps_buffers_with_the_same_layout(rb, workload):
         plan.update(bad)
 
 
+def test_pitched_maps(rb):
+    """Jobs on maps stored with row padding (pitch > width, NaN padding that
+    must never be read), hard and RSMSS, in one plan: each equals the plain
+    entry point and the oracle on the unpadded map."""
+    c = synth.make_config(2, 2011, small=True)
+    H, W = c["map"].shape
+    full = torch.full((H, W + 13), float("nan"), dtype=torch.float32, device="cuda")
+    full[:, :W] = torch.from_numpy(c["map"]).cuda()
+    view = full[:, :W]
+    f = torch.from_numpy(c["frags"]).cuda()
+    n = len(c["frags"])
+    jobs = [dict(map=view, frags=f, params=dict(c["params"], pitch=None), mode=0,
+                 out=torch.empty(n, dtype=torch.uint8, device="cuda")),
+            dict(map=view, frags=f, params=dict(c["params"], pitch=None), mode=1,
+                 out=torch.empty(n, dtype=torch.float32, device="cuda"))]
+    plan = rb.Plan(jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    p = dict(c["params"], pitch=W)
+    assert np.array_equal(jobs[0]["out"].cpu().numpy(), oracle.rbsm_hard(c["map"], c["frags"], p))
+    soft = jobs[1]["out"].cpu().numpy()
+    assert np.max(np.abs(soft.astype(np.float64) - oracle.rsmss(c["map"], c["frags"], p))) <= 1e-5
+    assert np.array_equal(soft, rb.rsmss_visibility(view, f, dict(c["params"], pitch=None)).cpu().numpy())
+    plan.close()
+
+
 def test_full_size_workload_sampled_against_oracle(rb):
     """The batched workload at full size (16 maps up to 8192^2, 8 views up to
     4K, 66.5 M fragment evaluations) in the launch configuration the bench

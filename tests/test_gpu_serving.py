@@ -236,6 +236,32 @@ def test_poisson_arrivals_complete(rb, world):
     eng.close()
 
 
+def test_pitched_light(rb, world):
+    """A light registered as a row-padded view (pitch > width, NaN padding):
+    the engine's results equal the plain entry point's on the same view."""
+    m = world["maps"][1]
+    H, W = m.shape
+    full = torch.full((H, W + 7), float("nan"), dtype=torch.float32, device="cuda")
+    full[:, :W] = torch.from_numpy(m).cuda()
+    view = full[:, :W]
+    eng = rb.Engine(64 << 20, 4)
+    lid = eng.add_light(view)
+    w, h = world["views"][2]
+    f = world["dev_frags"][(1, 2)]
+    outs = [torch.empty(w * h, dtype=torch.uint8, device="cuda"), torch.empty(w * h, dtype=torch.float32,
+                                                                               device="cuda")]
+    t = eng.submit(w * h, [dict(light=lid, mode=0, frags=f, out=outs[0], max_dist=16, depth_bias=1e-4),
+                           dict(light=lid, mode=1, frags=f, out=outs[1], max_dist=16, depth_bias=1e-4)],
+                   view_width=w)
+    assert eng.wait(t, 60000) is not None
+    p = dict(width=W, height=H, depth_bias=1e-4, max_dist=16, view_width=w)
+    assert np.array_equal(outs[0].cpu().numpy(), rb.rbsm_visibility(view, f, p).cpu().numpy())
+    assert np.array_equal(outs[1].cpu().numpy(), rb.rsmss_visibility(view, f, p).cpu().numpy())
+    hp = dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=16, kernel_radius=0)
+    assert np.array_equal(outs[0].cpu().numpy(), oracle.rbsm_hard(m, world["frags"][(1, 2)], hp))
+    eng.close()
+
+
 def test_full_size_requests_sampled_against_oracle(rb):
     """Serving at full size: resident lights of 1024^2..8192^2 and views of
     720p..4K, as the bench runs them (device destinations, a composite per
