@@ -93,13 +93,14 @@ def test_rpcf_full_size_sampled(rb):
 
 
 @pytest.mark.parametrize("r,max_dist", [(1, 1), (1, 16), (3, 16), (7, 16), (15, 16), (2, 29), (30, 1),
-                                        (2, 40), (6, 64)])
+                                        (2, 40), (6, 64), (31, 4), (32, 2)])
 def test_rpcf_radii_and_reach(rb, r, max_dist):
-    """Every RPCF route: staged box (screen tiles), words from global memory
-    (box too large), and the per-term form when r + MAXDIST exceeds a word."""
+    """Every RPCF route: staged bands (screen tiles), reads from global memory
+    (bands too large), and the per-term form when a column of 2r+3 rows no
+    longer fits one word (r > 30)."""
     c = synth.make_config(3, 3005, small=True)
     n = len(c["frags"])
-    idx = np.arange(0, n, max(1, n // (4000 if r <= 7 else 800)))
+    idx = np.arange(0, n, max(1, n // (4000 if r <= 7 else (800 if r <= 15 else 200))))
     p = dict(c["params"], kernel_radius=r, max_dist=max_dist)
     say(f"rpcf r={r} maxd={max_dist} n={n}")
     got = rb.rsmss_visibility(dev(c["map"]), dev(c["frags"]), p).cpu().numpy()
