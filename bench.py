@@ -433,6 +433,30 @@ def raster_section(torch, rb, seed: int = 5001, reps: int = 10):
     return {"workload": "64 random triangles over a tilted receiver, binary64 coverage", "maps": res}
 
 
+def composite_section(torch, rb, reps: int = 50):
+    """Multi-light compositing of one 4K view: 2 hard masks and 2 RSMSS
+    visibilities (1 + 1 + 4 + 4 bytes per fragment in) into a float32 shadow
+    buffer (4 bytes out); time per launch and bandwidth against HBM."""
+    n = 3840 * 2160
+    g = torch.Generator(device="cuda").manual_seed(9)
+    vis = [(torch.rand(n, device="cuda", generator=g) < 0.5).to(torch.uint8) for _ in range(2)]
+    vis += [torch.rand(n, device="cuda", generator=g) for _ in range(2)]
+    modes, weights = [0, 0, 1, 1], [0.4, 0.3, 0.2, 0.1]
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    rb.rbsm_composite(vis, modes, weights, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rb.rbsm_composite(vis, modes, weights, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = n * (1 + 1 + 4 + 4 + 4)
+    return {"workload": "4 lights (2 hard, 2 RSMSS) composited over one 3840x2160 view", "ms": ms,
+            "bytes_per_launch": nbytes, "achieved_GBps": nbytes / (ms * 1e-3) / 1e9, "hbm_peak_GBps": 8000.0}
+
+
 def cpu_baseline(frames: Frames, budget_s: float):
     """The oracle (single-threaded C, unchanged) on a bounded sample of the
     same frames: first on one core, then fanned out over the host's cores by
@@ -597,6 +621,7 @@ def main():
         out["serving"] = serving_section(torch, rb)
         torch.cuda.empty_cache()
         out["raster"] = raster_section(torch, rb)
+        out["composite"] = composite_section(torch, rb)
         torch.cuda.empty_cache()
         frames = Frames.__new__(Frames)  # host frames for the CPU leg
         import synth
