@@ -307,6 +307,40 @@ def test_all_edge_fragments_fill_the_queue(rb):
         check_soft(m, f, p, rb.rsmss_visibility(dev(m), dev(f), p).cpu().numpy())
 
 
+def test_largest_fragment_count(rb):
+    """n = 2^31 - 1 fragments (the largest the boundary accepts: 25.8 GB of
+    fragments, a ragged last tile), flat layout, hard, RSMSS and RPCF:
+    sampled outputs, the last ones included, against the oracle."""
+    c = synth.make_config(1, 1021, small=True)
+    m = c["map"]
+    n = 2 ** 31 - 1
+    say(f"n = {n}: generating")
+    g = torch.Generator(device="cuda").manual_seed(21)
+    f = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    f[:, 0].uniform_(-0.02, 1.02, generator=g)
+    f[:, 1].uniform_(-0.02, 1.02, generator=g)
+    f[:, 2].uniform_(0.3, 0.95, generator=g)
+    md = dev(m)
+    p = dict(c["params"], view_width=0)
+    rng = np.random.default_rng(22)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 3000), np.arange(n - 1100, n)]))
+    ti = torch.from_numpy(idx).cuda()
+    fs = f[ti].cpu().numpy()
+    say("n = 2^31 - 1: hard")
+    got = rb.rbsm_visibility(md, f, p)
+    check_hard(m, fs, p, got[ti].cpu().numpy())
+    del got
+    say("n = 2^31 - 1: rsmss")
+    got = rb.rsmss_visibility(md, f, p)
+    check_soft(m, fs, p, got[ti].cpu().numpy())
+    say("n = 2^31 - 1: rpcf r=1")
+    pr = dict(p, kernel_radius=1)
+    got = rb.rsmss_visibility(md, f, pr, out=got)
+    check_soft(m, fs, pr, got[ti].cpu().numpy())
+    del got, f
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("horizontal", [True, False])
 def test_long_walks_overflow_the_continuation_queue(rb, horizontal):
     """Stripes one texel wide: every fragment is an edge fragment whose walks
