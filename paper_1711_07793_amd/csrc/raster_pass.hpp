@@ -13,14 +13,16 @@
 // arithmetic is binary64 without contraction, so decisions are reproducible
 // exactly.
 //
-// One workgroup per 32 x 32 texel tile (64 x 64 on maps of 2^25 texels or
-// more, which amortizes the classification).  Each primitive is classified
-// against the tile's rectangle of texel centres, with a margin far above the
-// binary64 rounding of the edge functions: covering none (so every per-texel
-// test would fail), covering every one (every test would pass), or partial.  The covering ones reduce to one tile-wide nearest
-// depth; only the partial ones, listed in LDS, are tested per texel.  The
-// winner among equal depths is decided by primitive index, so the result
-// does not depend on the order of either list.
+// One workgroup per texel tile: 32 x 32 (256 threads), 16 x 16 (64 threads)
+// on maps under 2^22 texels so the grid still fills the GPU, 64 x 64 on maps
+// of 2^25 texels or more to amortize the classification.  Each primitive is
+// classified against the tile's rectangle of texel centres, with a margin far
+// above the binary64 rounding of the edge functions: covering none (so every
+// per-texel test would fail), covering every one (every test would pass), or
+// partial.  The covering ones reduce to one tile-wide nearest depth; only the
+// partial ones, listed in LDS, are tested per texel.  The winner among equal
+// depths is decided by primitive index, so the result does not depend on the
+// order of either list.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,8 +33,8 @@
 
 namespace rbsm {
 
-constexpr int kRasT = 256;      // threads per workgroup
-constexpr int kRasTile = 32;    // tile side in texels on smaller maps; a thread owns 4 texels of a row
+constexpr int kRasT = 256;      // threads per workgroup (32 x 32 and 64 x 64 tiles)
+constexpr int kRasTile = 32;    // tile side in texels on mid-size maps; a thread owns 4 texels of a row
 constexpr int kRasList = 2048;  // primitives listed per tile before falling back to all
 
 __device__ __forceinline__ double edge_value(double ax, double ay, double bx, double by, double px, double py) {
@@ -112,8 +114,8 @@ __device__ __forceinline__ int tile_cover(const rbsm_prim &q, double u0, double 
 // receiver plane): smaller, or equal and of lower index.
 __device__ __forceinline__ bool beats(float z, int k, float d, int idx) { return z < d || (z == d && k < idx); }
 
-template <int TS>
-__global__ __launch_bounds__(kRasT) void raster_kernel(const rbsm_prim *__restrict__ prims, int n, double r0,
+template <int TS, int NT>
+__global__ __launch_bounds__(NT) void raster_kernel(const rbsm_prim *__restrict__ prims, int n, double r0,
                                                        double ru, double rv, int W, int H, int64_t pitch,
                                                        float *__restrict__ map, int tiles_x) {
     __shared__ int s_list[kRasList];  // partly covering primitives
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(kRasT) void raster_kernel(const rbsm_prim *__restri
         s_nfull = 0;
     }
     __syncthreads();
-    for (int k = t; k < n; k += kRasT) {
+    for (int k = t; k < n; k += NT) {
         const rbsm_prim &q = prims[k];
         if (!may_touch(q, u0, u1, v0, v1, pad)) continue;
         const int c = tile_cover(q, u0, u1, v0, v1);
@@ -157,8 +159,8 @@ __global__ __launch_bounds__(kRasT) void raster_kernel(const rbsm_prim *__restri
             fk = k;
         }
     }
-    // each thread resolves 4 texels of a row, TS * TS / (4 kRasT) rows apart
-    constexpr int RP = kRasT / (TS / 4);  // rows per pass
+    // each thread resolves 4 texels of a row, NT / (TS / 4) rows apart
+    constexpr int RP = NT / (TS / 4);  // rows per pass
     const int col = i0 + (t % (TS / 4)) * 4;
     for (int row = j0 + t / (TS / 4); row <= j1; row += RP) {
         const double py = (row + 0.5) / H;
@@ -192,18 +194,22 @@ __global__ __launch_bounds__(kRasT) void raster_kernel(const rbsm_prim *__restri
 
 inline void launch_raster(const rbsm_prim *prims, int n, double r0, double ru, double rv, int W, int H, int64_t pitch,
                           float *map, hipStream_t stream) {
-    // large maps: 64 x 64 tiles amortize the classification over more texels
-    // while still giving 8192+ workgroups (4 per resident slot)
-    const bool big = (int64_t)W * H >= (int64_t)8192 * 4096;
-    const int ts = big ? 64 : kRasTile;
+    // tiles sized so the grid has several workgroups per resident slot: 16 x 16
+    // (64 threads) on maps under 2^22 texels, 64 x 64 on maps of 2^25 or more
+    // (which amortizes the classification), else 32 x 32
+    const int64_t area = (int64_t)W * H;
+    const int ts = area < ((int64_t)1 << 22) ? 16 : (area >= ((int64_t)1 << 25) ? 64 : kRasTile);
     const int tiles_x = (W + ts - 1) / ts, tiles_y = (H + ts - 1) / ts;
     const dim3 grid((unsigned)((int64_t)tiles_x * tiles_y));
-    if (big)
-        hipLaunchKernelGGL(raster_kernel<64>, grid, dim3(kRasT), 0, stream, prims, n, r0, ru, rv, W, H, pitch, map,
+    if (ts == 16)
+        hipLaunchKernelGGL((raster_kernel<16, 64>), grid, dim3(64), 0, stream, prims, n, r0, ru, rv, W, H, pitch, map,
                            tiles_x);
+    else if (ts == 64)
+        hipLaunchKernelGGL((raster_kernel<64, kRasT>), grid, dim3(kRasT), 0, stream, prims, n, r0, ru, rv, W, H,
+                           pitch, map, tiles_x);
     else
-        hipLaunchKernelGGL(raster_kernel<kRasTile>, grid, dim3(kRasT), 0, stream, prims, n, r0, ru, rv, W, H, pitch,
-                           map, tiles_x);
+        hipLaunchKernelGGL((raster_kernel<kRasTile, kRasT>), grid, dim3(kRasT), 0, stream, prims, n, r0, ru, rv, W,
+                           H, pitch, map, tiles_x);
 }
 
 }  // namespace rbsm
