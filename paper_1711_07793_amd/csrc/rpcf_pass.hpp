@@ -12,9 +12,13 @@
 // (Listing 3), normalization (Eq. 5) and Listing 5; their number varies
 // wildly between fragments, so such terms of each pair of columns are compacted
 // over the workgroup into an LDS list and evaluated one lane per term, keeping
-// every lane busy instead of holding a wave for its busiest fragment.  The
-// traversals read the two staged bands directly, the first two steps of all
-// four at once.
+// every lane busy instead of holding a wave for its busiest fragment.  A
+// vertical traversal is first resolved on the fragment's column words, which
+// hold the shadow-test bits of every row it can reach inside the kernel's
+// window; horizontal ones take their first two steps from a staged band.  The
+// bands reach only a few steps past the window, which keeps the workgroup's
+// LDS small enough for more of them per CU; the few longer traversals go on
+// in global memory.
 //
 // The sum is kept in binary64 (exact for these terms in practice) and divided
 // by (2r+1)^2 once, so the result is the box average rounded to binary32 once.
@@ -32,6 +36,7 @@ constexpr int kRpcfT = 128;    // threads per workgroup, one fragment each
 constexpr int kRpcfLaneBits = kRpcfT > 128 ? 8 : 7;  // lane field of a listed term
 constexpr int kRpcfMaxR = 30;  // largest r whose 2r+3 rows fit one 64-bit column word
 constexpr int kRpcfEnt = 512;  // terms with a discontinuity evaluated per round
+constexpr int kRpcfReach = 3;  // traversal steps staged beyond the kernel radius
 
 // Any radius: one lane per fragment, every term evaluated from global memory
 // in the same a-major order, binary64 sum.
@@ -98,6 +103,19 @@ struct BandWalkReader {
     }
 };
 
+// A map line and its two side lines (rows c, a, b when horizontal, columns
+// when not), read from global memory with clamp-to-edge.
+struct MapLineReader {
+    MapView m;
+    int c, a, b;
+    bool horiz;
+    __device__ __forceinline__ void operator()(int p, float &tc, float &ta, float &tb) const {
+        tc = horiz ? texel(m, p, c) : texel(m, c, p);
+        ta = horiz ? texel(m, p, a) : texel(m, a, p);
+        tb = horiz ? texel(m, p, b) : texel(m, b, p);
+    }
+};
+
 // The first two steps of a traversal (Listing 3) from a staged band, with no
 // branches so that the reads of all four traversals of a term can be in
 // flight together: +k / -k for the first stopping step, 0 if neither stops.
@@ -113,10 +131,55 @@ __device__ __forceinline__ int first_steps(const BandWalkReader &br, int p0, int
     return end1 ? 1 : (share1 ? at2 : -1);
 }
 
+// A vertical traversal (Listing 3) of the term in row q of column word w
+// (left and right neighbours wl, wr; bit 1 = in shadow), as far as the word
+// reaches: step k ends the walk when bit q+k of w equals s (the texel's test
+// differs from the term's) and stops it when, besides, no checked neighbour
+// bit equals s.  Returns +k / -k for the first stopping step, -(maxd+1) when
+// the walk runs out of steps inside the word, or 0 with `next` set to the
+// first step past the word.
+__device__ __forceinline__ uint64_t stop_bits(uint64_t wl, uint64_t w, uint64_t wr, bool s, bool chk_l, bool chk_r,
+                                              uint64_t &end) {
+    const uint64_t flip = s ? 0ull : ~0ull;
+    end = w ^ flip;
+    const uint64_t share = (chk_l ? wl ^ flip : 0ull) | (chk_r ? wr ^ flip : 0ull);
+    return end | ~share;
+}
+
+__device__ __forceinline__ int column_walk_up(uint64_t wl, uint64_t w, uint64_t wr, int q, int nbc, int maxd, bool s,
+                                              bool chk_l, bool chk_r, int &next) {
+    uint64_t end;
+    const uint64_t stop = stop_bits(wl, w, wr, s, chk_l, chk_r, end);
+    const int kn = min(nbc - 1 - q, maxd);  // steps inside the word, >= 1
+    const uint64_t b = (stop >> (q + 1)) & ((1ull << kn) - 1ull);
+    next = kn + 1;
+    if (b != 0ull) {
+        const int k = __builtin_ctzll(b) + 1;
+        return (end >> (q + k)) & 1ull ? k : -k;
+    }
+    return kn == maxd ? -(maxd + 1) : 0;
+}
+
+__device__ __forceinline__ int column_walk_down(uint64_t wl, uint64_t w, uint64_t wr, int q, int maxd, bool s,
+                                                bool chk_l, bool chk_r, int &next) {
+    uint64_t end;
+    const uint64_t stop = stop_bits(wl, w, wr, s, chk_l, chk_r, end);
+    const int kn = min(q, maxd);  // steps inside the word (rows q-1 .. q-kn), >= 1
+    const uint64_t b = stop & (((1ull << kn) - 1ull) << (q - kn));
+    next = kn + 1;
+    if (b != 0ull) {
+        const int p = 63 - __builtin_clzll(b);  // nearest stopping row below q
+        const int k = q - p;
+        return (end >> p) & 1ull ? k : -k;
+    }
+    return kn == maxd ? -(maxd + 1) : 0;
+}
+
 // One workgroup per TW x (kRpcfT / TW) pixel tile of a row-major image of
-// width vw (flat: vw = n, TW = kRpcfT).  With R = r + maxd, the texels every
-// word and traversal of the tile reads lie in two bands, staged in LDS (with
-// canon() applied) when both fit in `cap` texels:
+// width vw (flat: vw = n, TW = kRpcfT).  With R = r + min(maxd, kRpcfReach),
+// the texels every word and the first R - r steps of every traversal read lie
+// in two bands, staged in LDS (with canon() applied) when both fit in `cap`
+// texels; longer traversals go on in global memory:
 //   H: rows of the fragments' texel box grown by r+1, columns grown by R
 //      (row-major; horizontal traversals);
 //   V: columns grown by r+1, rows grown by R, stored transposed, each column
@@ -135,6 +198,7 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     __shared__ float s_ffx[kRpcfT], s_ffy[kRpcfT], s_fzb[kRpcfT];
     __shared__ uint32_t s_ent[kRpcfEnt];  // lane | q << LB | lit << (LB+6) | mask << (LB+7) | column << (LB+11)
     __shared__ float s_val[kRpcfEnt];
+    __shared__ uint64_t s_cw[4][kRpcfT];  // this round's column words a-1 .. a+2 of each fragment
     constexpr int TH = kRpcfT / TW, LB = kRpcfLaneBits;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t tile = xcd_block(blockIdx.x, gridDim.x);
@@ -144,7 +208,7 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     const bool valid = px < vw && k < n;
     Addr A{};
     if (valid) A = address(frags[3 * k + 0], frags[3 * k + 1], frags[3 * k + 2], m.W, m.H, bias);
-    const int R = r + maxd;
+    const int R = r + min(maxd, kRpcfReach);
 
     // texel box of the tile's fragments
     int b0 = valid ? A.i0 : INT32_MAX, b1 = valid ? -A.i0 : INT32_MAX;
@@ -254,6 +318,11 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
         }
         const int par = ((a + r) >> 1) & 1;  // double buffer: no barrier between rounds without such terms
         if (lane == 63) s_wtot[par][wave] = inc;
+        // the previous round's readers of s_cw all passed its last barrier
+        s_cw[0][t] = cm;
+        s_cw[1][t] = c0;
+        s_cw[2][t] = c1;
+        s_cw[3][t] = c2;
         __syncthreads();
         int off = inc - ne, tot = 0;
         for (int w = 0; w < kRpcfT / 64; ++w) {
@@ -309,17 +378,33 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
                     const bool vl = (mk & BIT_L) != 0, vr = (mk & BIT_R) != 0;
                     rd[0] = first_steps(bh, ph0, -1, maxd, zb, s, ht, hbt);
                     rd[1] = first_steps(bh, ph0, 1, maxd, zb, s, ht, hbt);
-                    rd[2] = first_steps(bv, pv0, 1, maxd, zb, s, vl, vr);
-                    rd[3] = first_steps(bv, pv0, -1, maxd, zb, s, vl, vr);
+                    // vertical traversals over the fragment's column words
+                    // (rows j0-r-1 .. j0+r+1) as far as they reach
+                    int k0[4] = {3, 3, 0, 0};
+                    {
+                        const int x = (en >> (LB + 11)) & 1u;
+                        const uint64_t wl = s_cw[x][L], w = s_cw[x + 1][L], wr = s_cw[x + 2][L];
+                        rd[2] = column_walk_up(wl, w, wr, q, nbc, maxd, s, vl, vr, k0[2]);
+                        rd[3] = column_walk_down(wl, w, wr, q, maxd, s, vl, vr, k0[3]);
+                    }
                     // the few that run on
                     for (int dir = 0; dir < 4; ++dir) {
                         if (rd[dir] != 0) continue;
                         const bool horiz = dir < 2;
                         const int d = dir == 0 || dir == 3 ? -1 : 1;
+                        const int p0 = horiz ? ph0 : pv0;
+                        const bool ca = horiz ? ht : vl, cb = horiz ? hbt : vr;
+                        // last step inside the band
+                        const int kl = min(maxd, d > 0 ? (horiz ? hw : vh) - 1 - p0 : p0);
                         int x = 0;
-                        if (maxd > 2)
-                            x = walk_range<4>(horiz ? bh : bv, 3, maxd, horiz ? ph0 : pv0, d, INT32_MAX / 4, zb, s,
-                                              horiz ? ht : vl, horiz ? hbt : vr);
+                        if (k0[dir] <= kl)
+                            x = walk_range<4>(horiz ? bh : bv, k0[dir], kl, p0, d, INT32_MAX / 4, zb, s, ca, cb);
+                        if (x == 0 && kl < maxd) {
+                            const MapLineReader g{m, horiz ? j : i, horiz ? j + 1 : i - 1, horiz ? j - 1 : i + 1,
+                                                  horiz};
+                            x = walk_range<4>(g, max(k0[dir], kl + 1), maxd, horiz ? i : j, d,
+                                              horiz ? m.W - 1 : m.H - 1, zb, s, ca, cb);
+                        }
                         rd[dir] = x != 0 ? x : -(maxd + 1);
                     }
                 } else {
@@ -347,9 +432,9 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
 // whose texel footprint spans up to 13 x 17 texels, within 64 KiB with the
 // kernel's static LDS.
 inline int rpcf_cap(int r, int maxd) {
-    const int R = r + maxd;
+    const int R = r + (maxd < kRpcfReach ? maxd : kRpcfReach);
     const int want = (12 + 2 * R + 1) * (16 + 2 * r + 3) + (12 + 2 * r + 3) * ((16 + 2 * R + 1 + 7) | 1);
-    const int room = (65536 - 10240) / 4;
+    const int room = (65536 - 12288) / 4;
     return want < room ? want : room;
 }
 

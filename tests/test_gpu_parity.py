@@ -194,6 +194,42 @@ def test_adversarial_maps(rb, name, max_dist):
     check_soft(m, f, p, rb.rsmss_visibility(md, fd, p).cpu().numpy())
 
 
+def _screen_frags(W, H, vw, vh, seed, spill=0.05):
+    """Fragments of a vw x vh view in row-major order, its pixels spread over
+    the map with a little jitter, so screen tiles cover compact texel boxes."""
+    rng = np.random.default_rng(seed)
+    x, y = np.meshgrid(np.arange(vw), np.arange(vh))
+    u = (x.ravel() + rng.uniform(0.2, 0.8, vw * vh)) / vw * (1 + 2 * spill) - spill
+    v = (y.ravel() + rng.uniform(0.2, 0.8, vw * vh)) / vh * (1 + 2 * spill) - spill
+    z = rng.choice(np.array([0.4, 0.6, 0.8, 0.95], np.float32), vw * vh)
+    return np.stack([u, v, z], 1).astype(np.float32)
+
+
+def _long_edge_map():
+    m = np.full((96, 96), 0.9, np.float32)
+    m[10:70, 15:80] = 0.5
+    m[75:90, 5:92] = 0.3
+    m[20:60, 85:96] = 0.6
+    m[0:4, :] = 0.7
+    return m
+
+
+@pytest.mark.parametrize("name", ["long_edges", "bars", "border", "checker2"])
+def test_rpcf_long_traversals_leave_the_staged_band(rb, name):
+    """Screen-ordered fragments (staged bands) over maps with long straight
+    edges: traversals run past the steps staged beside the kernel's texels
+    and go on in global memory, up to the map borders."""
+    m = _long_edge_map() if name == "long_edges" else _adversarial_maps()[name]
+    H, W = m.shape
+    f = _screen_frags(W, H, 160, 120, seed=H + len(name))
+    md, fd = dev(m), dev(f)
+    for r, max_dist in ((2, 40), (5, 64), (3, 9), (1, 63)):
+        say(f"rpcf long {name} r={r} maxd={max_dist}")
+        p = dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=max_dist, kernel_radius=r, view_width=160)
+        got = rb.rsmss_visibility(md, fd, p).cpu().numpy()
+        check_soft(m, f, p, got, np.arange(0, len(f), 3))
+
+
 def test_pitch_and_nonsquare_and_tiny_maps(rb):
     rng = np.random.default_rng(3)
     for (H, W, pitch) in [(1, 1, 1), (1, 7, 9), (5, 1, 4), (37, 53, 64), (200, 130, 131)]:
