@@ -22,7 +22,8 @@
 // partial.  The covering ones reduce to one tile-wide nearest depth; only the
 // partial ones, listed in LDS, are tested per texel.  The winner among equal
 // depths is decided by primitive index, so the result does not depend on the
-// order of either list.
+// order of either list.  A thread writes its 4 texels of a row with one
+// 16-byte store when rows start 16-byte aligned.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -117,7 +118,7 @@ __device__ __forceinline__ bool beats(float z, int k, float d, int idx) { return
 template <int TS, int NT>
 __global__ __launch_bounds__(NT) void raster_kernel(const rbsm_prim *__restrict__ prims, int n, double r0,
                                                        double ru, double rv, int W, int H, int64_t pitch,
-                                                       float *__restrict__ map, int tiles_x) {
+                                                       float *__restrict__ map, int tiles_x, bool vec) {
     __shared__ int s_list[kRasList];  // partly covering primitives
     __shared__ int s_full[kRasList];  // primitives covering every centre
     __shared__ int s_count, s_nfull;
@@ -187,8 +188,12 @@ __global__ __launch_bounds__(NT) void raster_kernel(const rbsm_prim *__restrict_
                 }
         }
         float *dst = map + (int64_t)row * pitch + col;
-        for (int e = 0; e < 4; ++e)
-            if (col + e <= i1) dst[e] = d[e];
+        if (vec && col + 3 <= i1) {  // one 16-byte store
+            *(float4 *)dst = make_float4(d[0], d[1], d[2], d[3]);
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (col + e <= i1) dst[e] = d[e];
+        }
     }
 }
 
@@ -201,15 +206,17 @@ inline void launch_raster(const rbsm_prim *prims, int n, double r0, double ru, d
     const int ts = area < ((int64_t)1 << 22) ? 16 : (area >= ((int64_t)1 << 25) ? 64 : kRasTile);
     const int tiles_x = (W + ts - 1) / ts, tiles_y = (H + ts - 1) / ts;
     const dim3 grid((unsigned)((int64_t)tiles_x * tiles_y));
+    // rows start 16-byte aligned: a thread's 4 texels (columns 4k .. 4k+3) are one float4
+    const bool vec = ((uintptr_t)map & 15u) == 0 && (pitch & 3) == 0;
     if (ts == 16)
         hipLaunchKernelGGL((raster_kernel<16, 64>), grid, dim3(64), 0, stream, prims, n, r0, ru, rv, W, H, pitch, map,
-                           tiles_x);
+                           tiles_x, vec);
     else if (ts == 64)
         hipLaunchKernelGGL((raster_kernel<64, kRasT>), grid, dim3(kRasT), 0, stream, prims, n, r0, ru, rv, W, H,
-                           pitch, map, tiles_x);
+                           pitch, map, tiles_x, vec);
     else
         hipLaunchKernelGGL((raster_kernel<kRasTile, kRasT>), grid, dim3(kRasT), 0, stream, prims, n, r0, ru, rv, W,
-                           H, pitch, map, tiles_x);
+                           H, pitch, map, tiles_x, vec);
 }
 
 }  // namespace rbsm

@@ -84,6 +84,24 @@ def test_padded_tiny_and_empty(rb):
     assert np.all(o[:, 40:] == -7.0)
 
 
+@pytest.mark.parametrize("pitch,offset", [(45, 0), (48, 1), (64, 2), (44, 0)])
+def test_row_alignment(rb, pitch, offset):
+    """Rows that start 16-byte aligned take one 4-texel store per thread, the
+    others texel by texel: both leave the same map and touch nothing past
+    the width."""
+    sc = synth.triangle_scene(612, 41, 37, 24, fence=True)
+    prims, rec = sc.primitives()
+    W, H = 41, 37
+    buf = torch.full((H * pitch + offset + 8,), -7.0, dtype=torch.float32, device="cuda")
+    out = buf[offset:offset + H * pitch].view(H, pitch)
+    rb.rbsm_rasterize(dev_prims(prims), rec, W, H, out=out)
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:, :W].view(np.uint32), oracle.raster(prims, rec, W, H).view(np.uint32))
+    assert np.all(o[:, W:] == -7.0)
+    b = buf.cpu().numpy()
+    assert np.all(b[:offset] == -7.0) and np.all(b[offset + H * pitch:] == -7.0)
+
+
 def test_thousands_of_overlapping_primitives(rb):
     """3000 large triangles over one 64^2 map: each tile sees all of them;
     those covering it whole fold into one depth, the rest are listed."""
