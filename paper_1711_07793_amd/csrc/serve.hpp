@@ -56,22 +56,50 @@ struct CompJob {
 
 constexpr int kCompT = 256, kCompF = 4;  // threads, fragments per thread
 
-__device__ __forceinline__ void composite_range(const CompJob &J, int64_t first) {
-    for (int e = 0; e < kCompF; ++e) {
-        const int64_t k = first + (int64_t)e * kCompT;
-        if (k >= J.n) return;
-        float acc = 0.0f;
+__device__ __forceinline__ float comp_value(const CompJob &J, int l, int64_t k) {
+    return J.hard[l] ? (float)static_cast<const uint8_t *>(J.vis[l])[k] : static_cast<const float *>(J.vis[l])[k];
+}
+
+// Each thread owns 4 consecutive fragments.  When every buffer of the job is
+// aligned for it (masks to 4 bytes, visibilities and the output to 16), each
+// light is one 4- or 16-byte load and the result one 16-byte store; otherwise,
+// and at a ragged end, fragment by fragment.  Either way a fragment's sum runs
+// over the lights in order with the same operations.
+__device__ __forceinline__ void composite_range(const CompJob &J, int64_t block_first) {
+    const int64_t k = block_first + 4 * (int64_t)threadIdx.x;
+    if (k >= J.n) return;
+    bool vec = (((uintptr_t)J.out) & 15u) == 0;
+    for (int l = 0; l < J.n_lights; ++l) vec = vec && (((uintptr_t)J.vis[l]) & (J.hard[l] ? 3u : 15u)) == 0;
+    if (vec && k + 3 < J.n) {
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int l = 0; l < J.n_lights; ++l) {
-            const float v = J.hard[l] ? (float)static_cast<const uint8_t *>(J.vis[l])[k]
-                                      : static_cast<const float *>(J.vis[l])[k];
-            acc = acc + J.w[l] * v;
+            float v[4];
+            if (J.hard[l]) {
+                const uint32_t b = *(const uint32_t *)(static_cast<const uint8_t *>(J.vis[l]) + k);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (float)((b >> (8 * e)) & 255u);
+            } else {
+                const float4 f = *(const float4 *)(static_cast<const float *>(J.vis[l]) + k);
+                v[0] = f.x;
+                v[1] = f.y;
+                v[2] = f.z;
+                v[3] = f.w;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = acc[e] + J.w[l] * v[e];
         }
-        J.out[k] = acc;
+        *(float4 *)(J.out + k) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        return;
+    }
+    for (int e = 0; e < 4 && k + e < J.n; ++e) {
+        float acc = 0.0f;
+        for (int l = 0; l < J.n_lights; ++l) acc = acc + J.w[l] * comp_value(J, l, k + e);
+        J.out[k + e] = acc;
     }
 }
 
 __global__ __launch_bounds__(kCompT) void composite_kernel(CompJob J) {
-    composite_range(J, (int64_t)blockIdx.x * (kCompT * kCompF) + threadIdx.x);
+    composite_range(J, (int64_t)blockIdx.x * (kCompT * kCompF));
 }
 
 inline int64_t composite_blocks(int64_t n) { return (n + kCompT * kCompF - 1) / (kCompT * kCompF); }
@@ -104,7 +132,7 @@ __device__ __forceinline__ int find_job(const int64_t *first, int n, int64_t g) 
 __global__ __launch_bounds__(kCompT) void composite_batch_kernel(const CompArgs a) {
     const int64_t g = blockIdx.x;
     const int j = find_job(a.first, a.n_jobs, g);
-    composite_range(a.jobs[j], (g - a.first[j]) * (kCompT * kCompF) + threadIdx.x);
+    composite_range(a.jobs[j], (g - a.first[j]) * (kCompT * kCompF));
 }
 
 // The batched tile pass of a scheduling step, one launch per chunk of jobs of

@@ -128,6 +128,14 @@ def test_composite_entry_point_matches_oracle(rb):
     assert np.array_equal(got, want)
     one = rb.rbsm_composite([torch.from_numpy(h).cuda()], [0], [1.0]).cpu().numpy()
     assert np.array_equal(one, h.astype(np.float32))
+    # buffers that do not start aligned: fragment by fragment, the same sums
+    # (s = 4: aligned again, 4 fragments per load)
+    for s in (1, 2, 3, 4):
+        da, dh = torch.from_numpy(a).cuda(), torch.from_numpy(h).cuda()
+        out = torch.zeros(n + 4, dtype=torch.float32, device="cuda")
+        got = rb.rbsm_composite([da[s:], dh[s:], da[:n - s]], [1, 0, 1], w, out=out[s:n]).cpu().numpy()
+        assert np.array_equal(got, oracle.composite([a[s:], h[s:], a[:n - s]], w)), s
+        assert np.all(out[:s].cpu().numpy() == 0) and np.all(out[n:].cpu().numpy() == 0)
 
 
 def test_alone_and_in_the_mix_are_identical(rb, world):
