@@ -131,13 +131,11 @@ __device__ __forceinline__ int first_steps(const BandWalkReader &br, int p0, int
     return end1 ? 1 : (share1 ? at2 : -1);
 }
 
-// A vertical traversal (Listing 3) of the term in row q of column word w
-// (left and right neighbours wl, wr; bit 1 = in shadow), as far as the word
-// reaches: step k ends the walk when bit q+k of w equals s (the texel's test
-// differs from the term's) and stops it when, besides, no checked neighbour
-// bit equals s.  Returns +k / -k for the first stopping step, -(maxd+1) when
-// the walk runs out of steps inside the word, or 0 with `next` set to the
-// first step past the word.
+// Stop rows of a vertical traversal over the column words w (the term's
+// column) and wl, wr (its left and right neighbours), bit 1 = in shadow: bit
+// p of `end` is set where the texel of row p has a test that differs from the
+// term's s (its bit equals s), and bit p of the result where the walk stops
+// there: it ends, or no checked neighbour's texel differs from s.
 __device__ __forceinline__ uint64_t stop_bits(uint64_t wl, uint64_t w, uint64_t wr, bool s, bool chk_l, bool chk_r,
                                               uint64_t &end) {
     const uint64_t flip = s ? 0ull : ~0ull;
@@ -146,6 +144,10 @@ __device__ __forceinline__ uint64_t stop_bits(uint64_t wl, uint64_t w, uint64_t 
     return end | ~share;
 }
 
+// A vertical traversal (Listing 3) of the term in row q of column word w, as
+// far as the word reaches, up (rows q+1, ...) or down (rows q-1, ...): +k / -k
+// for the first stopping step, -(maxd+1) when the walk runs out of steps
+// inside the word, or 0 with `next` set to the first step past the word.
 __device__ __forceinline__ int column_walk_up(uint64_t wl, uint64_t w, uint64_t wr, int q, int nbc, int maxd, bool s,
                                               bool chk_l, bool chk_r, int &next) {
     uint64_t end;
