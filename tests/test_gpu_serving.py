@@ -138,6 +138,26 @@ def test_composite_entry_point_matches_oracle(rb):
         assert np.all(out[:s].cpu().numpy() == 0) and np.all(out[n:].cpu().numpy() == 0)
 
 
+@pytest.mark.parametrize("n_lights", [4, 8])
+def test_composite_full_4k_view(rb, n_lights):
+    """A whole 3840 x 2160 view, as the benchmark composites it: every
+    fragment bit-equal to the oracle, hard and RSMSS lights alternating."""
+    n = 3840 * 2160
+    say(f"composite 4K lights={n_lights}")
+    vis, modes = [], []
+    for l in range(n_lights):
+        u = synth.uniform_floats(500 + l, n)
+        if l % 2 == 0:
+            vis.append((u < 0.5).astype(np.uint8))
+            modes.append(0)
+        else:
+            vis.append(u)
+            modes.append(1)
+    w = list(synth.uniform_floats(600 + n_lights, n_lights) / n_lights)
+    got = rb.rbsm_composite([torch.from_numpy(v).cuda() for v in vis], modes, w).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), oracle.composite(vis, w).view(np.uint32))
+
+
 def test_alone_and_in_the_mix_are_identical(rb, world):
     say("serving: alone")
     alone, st_a = _run(rb, world, budget=256 << 20, max_inflight=8, burst=False)
