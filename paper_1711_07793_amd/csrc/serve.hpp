@@ -43,6 +43,7 @@ constexpr int kServeMaxReqs = 64;    // requests per scheduling step
 constexpr int kServeSlots = 2;       // steps whose compute may be pending
 constexpr int kArgJobs = 40;         // tile jobs per launch, passed in the kernel arguments
 constexpr int kArgComp = 20;         // composites per launch, passed in the kernel arguments
+constexpr int kServeTileW = 64;      // tile width of the merged jobs (as in the batched autotuner's choice)
 
 // One view's composite: out[k] = sum_l w[l] * vis_l[k].
 struct CompJob {
@@ -300,7 +301,7 @@ bool rbsm_engine::step_launch() {
                 const EngineReq *R = list[c].first;
                 const rbsm_request &q = R->req;
                 const rbsm_request_light &L = q.lights[list[c].second];
-                const JobLayout lay = job_layout(q.n, q.view_width, kDefaultTile.tile_w);
+                const JobLayout lay = job_layout(q.n, q.view_width, rbsm::kServeTileW);
                 if (lay.tiles == 0) continue;
                 JobDev &D = A.jobs[A.n_jobs];
                 D.m = R->maps[list[c].second];
@@ -319,7 +320,7 @@ bool rbsm_engine::step_launch() {
                 tiles += lay.tiles;
             }
             if (tiles == 0) continue;
-            hipLaunchKernelGGL((rbsm::serve_kernel<kDefaultTile.tile_w>), dim3((unsigned)tiles), dim3(kT), lds,
+            hipLaunchKernelGGL((rbsm::serve_kernel<rbsm::kServeTileW>), dim3((unsigned)tiles), dim3(kT), lds,
                                s_compute, A, kDefaultTile.apron, kDefaultTile.cap);
         }
     }
