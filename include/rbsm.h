@@ -89,8 +89,12 @@ int rbsm_visibility(const float *shadow_map, const float *frags, int64_t n, cons
  * fixed-size fake penumbra in [0, 1].  With p->kernel_radius = r > 0 the
  * result is the RPCF box average: the RSMSS value evaluated at each of the
  * (2r+1)^2 texels (i0+a, j0+b), |a|, |b| <= r, with the fragment's own
- * sub-texel position and depth, summed in a-major order in binary32 and
- * multiplied by 1/(2r+1)^2 (PCF over the filtered edge, Sec. 5.3).
+ * sub-texel position and depth, averaged (PCF over the filtered edge,
+ * Sec. 5.3): the exact mean of those binary32 values rounded to binary32.
+ * It is computed as a binary64 sum in an unspecified order divided once by
+ * (2r+1)^2, which stays within 5e-13 of the exact mean, so the result is the
+ * rounded exact mean except at a near-tie, where it may be the neighbouring
+ * binary32 value.
  *   out_vis     [n] float32 written: visibility in [0, 1], fragment order
  * Other arguments as rbsm_visibility.
  */

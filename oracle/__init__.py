@@ -8,8 +8,8 @@ no code.
 The arithmetic lives in ``rbsm_oracle.c`` (plain single-threaded C, binary32 in
 the paper's listing order, built with ``-ffp-contract=off``); this module only
 marshals numpy arrays through ctypes.  A second, independently structured
-implementation (``stencil.py``, whole-map numpy array operations) exists only to
-cross-check the C oracle on exhaustive tiny maps.
+implementation (``tests/stencil_rbsm.py``, whole-map numpy array operations)
+exists only to cross-check the C oracle on exhaustive tiny maps.
 """
 from __future__ import annotations
 

@@ -37,9 +37,15 @@
  *  - RPCF (radius r > 0): box average of the RSMSS value evaluated at the
  *    (2r+1)^2 texels around the fragment's texel with the same sub-texel
  *    position and depth (Sec. 5.3 suggests PCF to suppress skeleton artifacts).
- *    The paper fixes no summation order or precision, so the average is the
- *    plain definition: terms summed in binary64 (exact for these values in
- *    practice), divided by (2r+1)^2 in binary64, rounded to binary32 once.
+ *    The paper fixes no summation order or precision.  The result is defined
+ *    as the exact mean of the (2r+1)^2 binary32 terms rounded to binary32;
+ *    the oracle approximates that mean by summing the terms in binary64 in
+ *    row-major offset order (a outer, b inner), dividing once in binary64 and
+ *    rounding to binary32.  For M = (2r+1)^2 <= 4225 terms in [0, 1] the
+ *    binary64 sum is within (M - 1) M 2^-53 < 2e-9 of the exact sum in any
+ *    order, so any binary64 evaluation order lands within 5e-13 of the exact
+ *    mean before the final rounding: two orders give equal or adjacent
+ *    binary32 results.
  */
 #include <math.h>
 #include <stdint.h>
@@ -81,64 +87,54 @@ static float fetch(const float *map, const oracle_params *p, int i, int j) {
 /* Eq. 1: s = 0 if p_z > z(t), 1 otherwise (pz already carries the bias). */
 static float shadow_test(float pz, float blocker) { return pz > blocker ? 0.0f : 1.0f; }
 
-/* Eq. 2 / computeN: tests of the 4-connected neighbours at the same depth,
- * in the order left, right, top (+y), bottom (-y). */
-static void compute_N(const float *map, const oracle_params *p, int i, int j, float pz, float N[4]) {
-    N[0] = shadow_test(pz, fetch(map, p, i - 1, j));
-    N[1] = shadow_test(pz, fetch(map, p, i + 1, j));
-    N[2] = shadow_test(pz, fetch(map, p, i, j + 1));
-    N[3] = shadow_test(pz, fetch(map, p, i, j - 1));
+/* Eq. 2-3: the neighbour tests at the fragment's own depth and the
+ * discontinuity directions they give.  Bit L (1), R (2), T (4, +y) or B
+ * (8, -y) is set when that 4-connected neighbour's test differs from the
+ * texel's own test s. */
+enum { DIR_L = 1, DIR_R = 2, DIR_T = 4, DIR_B = 8 };
+
+static unsigned discontinuity_dirs(const float *map, const oracle_params *p, int i, int j, float pz,
+                                   float s) {
+    unsigned bits = 0;
+    if (shadow_test(pz, fetch(map, p, i - 1, j)) != s) bits |= DIR_L;
+    if (shadow_test(pz, fetch(map, p, i + 1, j)) != s) bits |= DIR_R;
+    if (shadow_test(pz, fetch(map, p, i, j + 1)) != s) bits |= DIR_T;
+    if (shadow_test(pz, fetch(map, p, i, j - 1)) != s) bits |= DIR_B;
+    return bits;
 }
 
-/* Eq. 3: uncompressed discontinuity |N - s|. */
-static void discontinuity_dirs(const float *map, const oracle_params *p, int i, int j, float pz,
-                               float s, float dU[4]) {
-    float N[4];
-    compute_N(map, p, i, j, pz, N);
-    for (int k = 0; k < 4; ++k) dU[k] = fabsf(N[k] - s);
-}
-
-/* Eq. 4: compressed discontinuity d = ((2 dL + dR)/4, (2 dT + dB)/4, 1 - s). */
-static void compress_discontinuity(const float dU[4], float s, float d[3]) {
-    d[0] = (2.0f * dU[0] + dU[1]) / 4.0f;
-    d[1] = (2.0f * dU[2] + dU[3]) / 4.0f;
+/* Eq. 4: the compressed discontinuity vector of Table 1,
+ * d = ((2 dL + dR) / 4, (2 dT + dB) / 4, 1 - s). */
+static void compress_discontinuity(unsigned bits, float s, float d[3]) {
+    const float dl = (bits & DIR_L) ? 1.0f : 0.0f, dr = (bits & DIR_R) ? 1.0f : 0.0f;
+    const float dt = (bits & DIR_T) ? 1.0f : 0.0f, db = (bits & DIR_B) ? 1.0f : 0.0f;
+    d[0] = (2.0f * dl + dr) / 4.0f;
+    d[1] = (2.0f * dt + db) / 4.0f;
     d[2] = 1.0f - s;
 }
 
-/* Do the visited texel and the fragment share a discontinuity direction? */
-static int check_discontinuity(const float *map, const oracle_params *p, int i, int j, float pz,
-                               float s, const float dU0[4]) {
-    float dU[4];
-    discontinuity_dirs(map, p, i, j, pz, s, dU);
-    for (int k = 0; k < 4; ++k)
-        if (dU0[k] == 1.0f && dU[k] == 1.0f) return 1;
-    return 0;
-}
-
-/* traverseShadowSilhouette: walk at most max_dist texels in (dx, dy).  The
- * distance starts at 1 and grows by one per step that stays on the edge; it
- * is returned positive when an end (a texel with the opposite test) was found
- * and negative otherwise. */
-static int traverse(const float *map, const oracle_params *p, int i0, int j0, float pz, float s,
-                    const float dU0[4], int dx, int dy) {
-    float shadow_edge_end = 0.0f;
-    int distance = 1;
-    int i = i0, j = j0;
-    for (int it = 0; it < p->max_dist; ++it) {
-        i += dx;
-        j += dy;
-        const float snp = shadow_test(pz, fetch(map, p, i, j));
-        if (snp != s) {
-            shadow_edge_end = 1.0f;
-            break;
-        }
-        if (!check_discontinuity(map, p, i, j, pz, s, dU0)) break;
-        distance++;
+/* Sec. 3.1.3: the distance from the fragment's texel to the end of its
+ * shadow edge in direction (dx, dy).  Texel k = 1, 2, ... max_dist along the
+ * direction either has the opposite test (the edge ends there: +k), or no
+ * longer shares a discontinuity direction with the fragment's texel (the
+ * edge leaves the direction without ending: -k); if neither happens within
+ * max_dist texels the edge is taken as unbounded, -(max_dist + 1). */
+static int edge_distance(const float *map, const oracle_params *p, int i0, int j0, float pz, float s,
+                         unsigned dirs0, int dx, int dy) {
+    for (int k = 1; k <= p->max_dist; ++k) {
+        const int i = i0 + k * dx, j = j0 + k * dy;
+        if (shadow_test(pz, fetch(map, p, i, j)) != s) return k;
+        if ((discontinuity_dirs(map, p, i, j, pz, s) & dirs0) == 0) return -k;
     }
-    return shadow_edge_end == 1.0f ? distance : -distance;
+    return -(p->max_dist + 1);
 }
 
-/* normalizeFragmentDistanceToSE for one axis (Eq. 5 and Sec. 3.1.4). */
+/* Sec. 3.1.4 and Eq. 5: one axis of the normalized discontinuity space,
+ * from the walks toward its negative and positive side.  The code counts the
+ * walks that found an end (two -> 1, one -> 0, none -> -1).  With exactly one
+ * end the coordinate is the fragment's distance to the boundary of the end
+ * texel over the number of edge texels on the axis; an axis without an end
+ * reads 1 and one with two ends 0 (that value is never used). */
 static void normalize_axis(int rd_neg, int rd_pos, float f, float *nrd, float *code) {
     const int ends = (rd_neg > 0) + (rd_pos > 0);
     if (ends == 2) {
@@ -157,13 +153,25 @@ static void normalize_axis(int rd_neg, int rd_pos, float f, float *nrd, float *c
     }
 }
 
-/* Listing 4: silhouette recovery visibility. */
-static float smsr_visibility(const float d[3], const float nrd[4]) {
-    if (d[0] == 0.75f || d[1] == 0.75f) return 0.0f;
-    if (nrd[2] == 1.0f || nrd[3] == 1.0f) return 0.0f;
-    if (nrd[2] == -1.0f || nrd[3] == -1.0f) return 1.0f;
-    const float edge = 1.0f - nrd[0];
-    return nrd[1] < edge ? 0.0f : 1.0f; /* step(1 - nrd.x, nrd.y) */
+/* Shape of the shadow edge at the fragment (Fig. 3; Sec. 3.1.4), read off
+ * each axis separately.  An axis is closed when the edge ends on both of its
+ * sides: either both neighbours on the axis already have the opposite test
+ * (d == 0.75, the short shapes of Sec. 4) or both walks along it found an
+ * end (code 1).  It is open when no walk along it found an end (code -1).
+ *   both axes closed               -> O
+ *   one axis closed                -> U (a ramp along the other axis)
+ *   otherwise, an open axis        -> I (a straight edge)
+ *   otherwise (one end per axis)   -> L (clipped by the revectorized edge) */
+typedef enum { SHAPE_O, SHAPE_U_ALONG_Y, SHAPE_U_ALONG_X, SHAPE_I, SHAPE_L } edge_shape;
+
+static edge_shape classify_shape(const float d[3], const float nrd[4]) {
+    const int x_closed = d[0] == 0.75f || nrd[2] == 1.0f;
+    const int y_closed = d[1] == 0.75f || nrd[3] == 1.0f;
+    if (x_closed && y_closed) return SHAPE_O;
+    if (x_closed) return SHAPE_U_ALONG_Y;
+    if (y_closed) return SHAPE_U_ALONG_X;
+    if (nrd[2] == -1.0f || nrd[3] == -1.0f) return SHAPE_I;
+    return SHAPE_L;
 }
 
 static float clamp01(float x) {
@@ -171,16 +179,46 @@ static float clamp01(float x) {
     return lo < 1.0f ? lo : 1.0f;
 }
 
-/* Listing 5: filtering visibility. */
-static float rsmss_visibility_fn(const float d[3], const float nrd[4]) {
-    const float sign = -2.0f * d[2] + 1.0f;
-    if (d[0] == 0.75f && d[1] == 0.75f) return d[2];
-    if (nrd[2] == 1.0f && nrd[3] == 1.0f) return d[2];
-    if (nrd[2] == 1.0f) return d[2] + sign * nrd[1];
-    if (nrd[3] == 1.0f) return d[2] + sign * nrd[0];
-    if (nrd[2] == -1.0f || nrd[3] == -1.0f) return 1.0f - d[2];
-    const float t = d[2] + sign * nrd[1];
-    return clamp01(t + sign * nrd[0]);
+/* Silhouette recovery (Sec. 3.1.4; the optimized function of Sec. 4) for a
+ * lit fragment on an edge: closed shapes are put in shadow, straight edges
+ * stay lit, and an L shape is shadowed below the revectorized edge, the line
+ * nrd.y = 1 - nrd.x (a point on the line stays lit). */
+static float hard_visibility(edge_shape shape, const float nrd[4]) {
+    switch (shape) {
+        case SHAPE_O:
+        case SHAPE_U_ALONG_X:
+        case SHAPE_U_ALONG_Y:
+            return 0.0f;
+        case SHAPE_I:
+            return 1.0f;
+        default:
+            return nrd[1] < 1.0f - nrd[0] ? 0.0f : 1.0f;
+    }
+}
+
+/* Revectorization-based filtering (Sec. 3.2; the optimized function of
+ * Sec. 4) for a fragment on an edge, lit or shadowed (d.z = 1 - s).  With
+ * sg = 1 - 2 d.z the value moves away from d.z by the normalized distances:
+ * an O shape keeps d.z, a U shape ramps along its open axis, a straight edge
+ * returns the test itself (1 - d.z), and an L shape adds both ramps, in the
+ * order y then x, clamped to [0, 1]. */
+static float filtered_visibility(edge_shape shape, const float d[3], const float nrd[4]) {
+    const float dz = d[2];
+    const float sg = 1.0f - 2.0f * dz;
+    switch (shape) {
+        case SHAPE_O:
+            return dz;
+        case SHAPE_U_ALONG_Y:
+            return dz + sg * nrd[1];
+        case SHAPE_U_ALONG_X:
+            return dz + sg * nrd[0];
+        case SHAPE_I:
+            return 1.0f - dz;
+        default: {
+            const float along_y = dz + sg * nrd[1];
+            return clamp01(along_y + sg * nrd[0]);
+        }
+    }
 }
 
 /* Everything the pass computes for one fragment at texel (i0, j0). */
@@ -199,31 +237,32 @@ typedef struct {
 static void rbsm_at(const float *map, const oracle_params *p, int i0, int j0, float fx, float fy,
                     float pz, int hard, oracle_detail *out) {
     memset(out, 0, sizeof(*out));
-    const float z = fetch(map, p, i0, j0);
-    const float s = shadow_test(pz, z);
+    /* Eq. 1 at the fragment's texel; silhouette recovery only ever works on
+     * the lit side, so a shadowed fragment stays shadowed */
+    const float s = shadow_test(pz, fetch(map, p, i0, j0));
     out->s = s;
     if (hard && s == 0.0f) {
         out->path = 0;
         out->vis = s;
         return;
     }
-    float dU[4];
-    discontinuity_dirs(map, p, i0, j0, pz, s, dU);
-    compress_discontinuity(dU, s, out->d);
-    if (!(out->d[0] > 0.0f || out->d[1] > 0.0f)) {
+    /* Eq. 2-4: no discontinuity means no shadow edge: the plain test */
+    const unsigned dirs0 = discontinuity_dirs(map, p, i0, j0, pz, s);
+    compress_discontinuity(dirs0, s, out->d);
+    if (dirs0 == 0) {
         out->path = 1;
         out->vis = s;
         return;
     }
-    /* computeFragmentDistanceToSE: left, right, top, bottom */
-    out->rd[0] = traverse(map, p, i0, j0, pz, s, dU, -1, 0);
-    out->rd[1] = traverse(map, p, i0, j0, pz, s, dU, +1, 0);
-    out->rd[2] = traverse(map, p, i0, j0, pz, s, dU, 0, +1);
-    out->rd[3] = traverse(map, p, i0, j0, pz, s, dU, 0, -1);
+    /* Sec. 3.1.3: distances to the edge ends, left, right, top, bottom */
+    const int step[4][2] = {{-1, 0}, {+1, 0}, {0, +1}, {0, -1}};
+    for (int w = 0; w < 4; ++w) out->rd[w] = edge_distance(map, p, i0, j0, pz, s, dirs0, step[w][0], step[w][1]);
+    /* Eq. 5: x from (left, right) and fx, y from (bottom, top) and fy */
     normalize_axis(out->rd[0], out->rd[1], fx, &out->nrd[0], &out->nrd[2]);
     normalize_axis(out->rd[3], out->rd[2], fy, &out->nrd[1], &out->nrd[3]);
     out->path = 2;
-    out->vis = hard ? smsr_visibility(out->d, out->nrd) : rsmss_visibility_fn(out->d, out->nrd);
+    const edge_shape shape = classify_shape(out->d, out->nrd);
+    out->vis = hard ? hard_visibility(shape, out->nrd) : filtered_visibility(shape, out->d, out->nrd);
 }
 
 /* Fragment addressing: texel and sub-texel fraction from (u, v). */
@@ -345,10 +384,12 @@ int oracle_multi(const float *maps, int64_t map_stride, const int32_t *map_index
 }
 
 /* Binary64 decision margin of one fragment: the smallest distance to a
- * decision boundary over the depth tests the pass performs, and, for a
- * revectorized fragment, over the L-line test |nrd.y - (1 - nrd.x)| and the
- * RSMSS clamp, all recomputed in binary64 from the same integer walk.
- * Used only to confirm that a GPU/oracle disagreement is a rounding tie. */
+ * decision boundary over every depth test the pass can perform for it (the
+ * texels on the two axes through its texel within max_dist + 1, and their
+ * side neighbours), and, for an L-shaped edge, over the revectorized-edge
+ * test |nrd.y - (1 - nrd.x)| recomputed in binary64 from the same integer
+ * walk.  Used only to confirm that a GPU/oracle disagreement of a hard mask
+ * is a rounding tie. */
 double oracle_margin_one(const float *map, const float *frag, const oracle_params *p, int hard) {
     if (!params_ok(p) || !frag_ok(p, frag)) return -1.0;
     int i0, j0;

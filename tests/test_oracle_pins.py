@@ -653,3 +653,165 @@ def test_raster_agrees_with_the_scene_generator(fence):
     q = synth.quad_scene(78, 128, 128)
     prims, rec = q.primitives()
     assert np.array_equal(oracle.raster(prims, rec, 128, 128), q.raster())
+
+
+# --------------------------------------------------------------------------
+# The binary64 decision margin (used to excuse hard-mask disagreements):
+# pinned by hand-placed near-boundary texels and by the closed form of the
+# revectorized edge in Fig. 3c
+# --------------------------------------------------------------------------
+
+FAR_LIT, FAR_BLOCK = np.float32(1.0), np.float32(0.25)
+
+
+def _straight_edge(W=64, j0=20):
+    """Rows below j0 blocked (0.25), the rest lit (1.0): a fragment at depth
+    0.75 in row j0 sits on an edge whose left and right walks run the full
+    MAXDIST (every visited texel shares the bottom discontinuity)."""
+    m = np.full((W, W), FAR_LIT, np.float32)
+    m[:j0, :] = FAR_BLOCK
+    return m
+
+
+@pytest.mark.parametrize("bias", [0.0, 2.0 ** -10])
+@pytest.mark.parametrize("hard", [True, False])
+def test_margin_single_near_boundary_texel(bias, hard):
+    W, i0, j0, md = 64, 20, 20, 16
+    z = np.float32(0.75 + bias)           # z - bias = 0.75 exactly
+    p = params(W, bias=bias, max_dist=md)
+    frag = np.array([(i0 + 0.375) / W, (j0 + 0.625) / W, z], np.float32)
+    base = oracle.margin(_straight_edge(W, j0), frag, p, hard)
+    assert base == 0.25                    # the lit texels 1.0 against 0.75
+    d = oracle.detail(_straight_edge(W, j0), frag, p, hard)
+    assert d.path == 2 and d.rd[0] == -(md + 1) and d.rd[1] == -(md + 1)
+    for delta in (2.0 ** -10, 2.0 ** -20):
+        placed = {
+            "centre": (i0, j0, 0.75 + delta),
+            "walk step MAXDIST": (i0 + md, j0, 0.75 + delta),
+            "walk step -MAXDIST": (i0 - md, j0, 0.75 + delta),
+            "side neighbour of a step": (i0 + 5, j0 - 1, 0.75 - delta),
+            "vertical walk, its side neighbour": (i0 + 1, j0 + 3, 0.75 + delta),
+        }
+        for what, (i, j, t) in placed.items():
+            m = _straight_edge(W, j0)
+            m[j, i] = np.float32(t)
+            # the placed texel keeps its test, so the walks are unchanged
+            dd = oracle.detail(m, frag, p, hard)
+            assert list(dd.rd) == list(d.rd), what
+            assert oracle.margin(m, frag, p, hard) == delta, what
+        for what, (i, j) in {"off the walk cross": (i0 + 2, j0 + 2),
+                             "beyond the reach": (i0 + md + 2, j0)}.items():
+            m = _straight_edge(W, j0)
+            m[j, i] = np.float32(0.75 + delta)
+            assert oracle.margin(m, frag, p, hard) == base, what
+
+
+def test_margin_revectorized_edge_closed_form():
+    """Fig. 3c: on the L window the edge line runs from (2,3) to (3,1); a lit
+    fragment at (x, y) in texel (2,1) or (2,2) has nrd.x = x - 2 and
+    nrd.y = (y - 1) / 2 (one end to the left, an edge two texels tall), so the
+    decision value is |(y - 1)/2 - (1 - (x - 2))|, capped by the depth margin."""
+    black, lit, _ = _fig3()["L"]
+    W, off = 16, 6
+    m = np.full((W, W), FAR_LIT, np.float32)
+    for x, y in black:
+        m[off + y, off + x] = np.float32(0.5)
+    p = params(W)
+    z = np.float32(0.875)  # depth margins 0.125 (lit) and 0.375 (blocked)
+    n_line = 0
+    for tx, ty in lit:
+        for a in range(16):
+            for b in range(16):
+                x, y = tx + (2 * a + 1) / 32.0, ty + (2 * b + 1) / 32.0
+                frag = np.array([(off + x) / W, (off + y) / W, z], np.float32)
+                line = abs((y - 1.0) / 2.0 - (1.0 - (x - 2.0)))
+                want = min(0.125, line)
+                assert oracle.margin(m, frag, p, True) == want, (x, y)
+                n_line += line < 0.125
+    assert n_line > 100
+
+
+# --------------------------------------------------------------------------
+# RSMSS continuity across straight edges (Sec. 3.2: the origin of the
+# normalized space stays at the edge, so the fake penumbra joins up at the
+# side between a lit and a shadowed texel)
+# --------------------------------------------------------------------------
+
+def test_rsmss_continuous_across_straight_edges():
+    rng = np.random.default_rng(3211)
+    W, md, eps = 64, 16, 2.0 ** -12
+    p = params(W, bias=1e-4, max_dist=md)
+    lo, hi = md + 2, W - md - 2
+    checked = 0
+    for _ in range(10):
+        while True:  # edges away from the axes: runs shorter than MAXDIST
+            theta = rng.uniform(0, 2 * np.pi)
+            if min(abs(np.sin(theta)), abs(np.cos(theta))) > 0.15:
+                break
+        n = np.array([np.cos(theta), np.sin(theta)])
+        c = n @ np.array([W / 2, W / 2]) + rng.uniform(-2, 2)
+        ii, jj = np.meshgrid(np.arange(W), np.arange(W))
+        inside = n[0] * (ii + 0.5) + n[1] * (jj + 0.5) < c
+        m = np.where(inside, BLOCK, LIT).astype(np.float32)
+        pairs_a, pairs_b = [], []
+        for j in range(lo, hi):
+            for i in range(lo, hi):
+                for t in (0.25, 0.5, 0.75):
+                    if inside[j, i] != inside[j - 1, i]:  # side y = j between (i, j-1) and (i, j)
+                        pairs_a.append(((i + t) / W, j / W))
+                        pairs_b.append(((i + t) / W, (j - eps) / W))
+                    if inside[j, i] != inside[j, i - 1]:  # side x = i
+                        pairs_a.append((i / W, (j + t) / W))
+                        pairs_b.append(((i - eps) / W, (j + t) / W))
+        fa = np.array([(u, v, 0.9) for u, v in pairs_a], np.float32)
+        fb = np.array([(u, v, 0.9) for u, v in pairs_b], np.float32)
+        va, vb = oracle.rsmss(m, fa, p), oracle.rsmss(m, fb, p)
+        # the two sides really are a lit and a shadowed texel
+        assert np.all(oracle.shadow_map(m, fa, p) != oracle.shadow_map(m, fb, p))
+        # |d nrd / d f| <= 1 per axis: the values may differ by eps, not more
+        assert np.max(np.abs(va - vb)) <= 2 * eps, theta
+        assert np.any((va > 0) & (va < 1))
+        checked += len(fa)
+    assert checked > 1000
+
+
+# --------------------------------------------------------------------------
+# RPCF: the correctly rounded exact mean of its terms
+# --------------------------------------------------------------------------
+
+def test_rpcf_is_the_rounded_exact_mean():
+    """The box average is defined as the exact mean of the (2r+1)^2 binary32
+    RSMSS terms rounded to binary32; the oracle's binary64 sum stays within
+    5e-13 of it, so its result is the correctly rounded exact mean except at
+    a near-tie.  Terms come from r = 0 evaluations of fragments shifted by
+    whole texels, with sub-texel positions that survive the shift exactly."""
+    from fractions import Fraction
+    m, fr = _random_scene(17, W=32, n_rect=8)
+    m = np.ascontiguousarray(m[:32, :32])
+    rng = np.random.default_rng(5)
+    k = 200
+    i = rng.integers(0, 32, k)
+    j = rng.integers(0, 32, k)
+    # fractions with bits down to 2^-18 (exact in binary32 for texels < 32)
+    fx = rng.integers(0, 1 << 18, k) / float(1 << 18)
+    fy = rng.integers(0, 1 << 18, k) / float(1 << 18)
+    fr = np.stack([(i + fx) / 32, (j + fy) / 32, fr[:k, 2]], 1).astype(np.float32)
+    for r in (1, 3):
+        p = params(32, bias=1e-4, max_dist=16, radius=r)
+        got = oracle.rsmss(m, fr, p)
+        p0 = dict(p, kernel_radius=0)
+        terms = []
+        for a in range(-r, r + 1):
+            for b in range(-r, r + 1):
+                sh = fr.copy()
+                sh[:, 0] = fr[:, 0] + np.float32(a / 32)
+                sh[:, 1] = fr[:, 1] + np.float32(b / 32)
+                terms.append(oracle.rsmss(m, sh, p0))
+        terms = np.array(terms)
+        M = (2 * r + 1) ** 2
+        for q in range(k):
+            exact = sum(Fraction(float(t)) for t in terms[:, q]) / M
+            g = float(got[q])
+            ulp = float(np.spacing(np.float32(g))) if g > 0 else 2.0 ** -149
+            assert abs(Fraction(g) - exact) <= Fraction(ulp) / 2 + Fraction(1, 10 ** 12), (r, q)
+        assert np.any((got > 0) & (got < 1))
