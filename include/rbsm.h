@@ -130,10 +130,20 @@ int rbsm_footprint(const float *shadow_map, const float *frags, int64_t n, const
  * project's autotuner searches.
  */
 typedef struct {
-    int32_t tile_w;   /* screen-tile width in pixels: 16, 32 or 64 (height 1024 / tile_w);
-                         ignored (flat 1024-fragment chunks) when view_width is 0 */
-    int32_t apron;    /* texels staged around the tile's texel box, 1..8 */
-    int32_t lds_cap;  /* LDS texel capacity per workgroup, 256..12288 */
+    int32_t tile_w;     /* screen-tile width in pixels: 16, 32 or 64 (height 1024 / tile_w);
+                           ignored (flat 1024-fragment chunks) when view_width is 0 */
+    int32_t apron;      /* texels staged around the tile's texel box, 1..8 */
+    int32_t lds_cap;    /* LDS texel capacity per workgroup, 256..12288 */
+    int32_t persistent; /* 0: one workgroup per screen tile; 1: only resident
+                           workgroups, each looping over tiles and loading the
+                           next tile's fragments while it works on the current one */
+    int32_t walk_first; /* traversal steps every walk takes before unfinished
+                           walks are regrouped: 1, 2 or 4 (0 = default 2) */
+    int32_t walk_block; /* steps per block of a regrouped walk, read together:
+                           4 or 8 (0 = default 4) */
+    int32_t xcd_chunk;  /* how tiles are dealt to the 8 XCDs: -1 one contiguous
+                           range each; c in 0..12: chunks of 2^c consecutive
+                           tiles round-robin (balances uneven jobs) */
 } rbsm_tuning;
 
 /* The tuning the plain entry points use. */
@@ -143,7 +153,9 @@ rbsm_tuning rbsm_default_tuning(void);
  * rbsm_visibility (mode 0, out = uint8_t[n]) or rsmss_visibility with
  * kernel_radius 0 (mode 1, out = float[n]) under an explicit tuning.
  * Arguments as those entry points; tune must be valid (RBSM_ERR_INVALID_ARG
- * otherwise).
+ * otherwise).  This entry point honours tile_w, apron, lds_cap and
+ * persistent; walk_first and walk_block must be 0 or their defaults (the
+ * walk blocking is searched in plans, whose kernels are built for each).
  */
 int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, int64_t n,
                     const rbsm_params *p, const rbsm_tuning *tune, void *out, hipStream_t stream);
@@ -180,10 +192,27 @@ int rbsm_plan_update(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs);
 /* Enqueue one batched pass on stream (graph replay after rbsm_plan_capture). */
 int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream);
 
-/* Time each candidate tuning (tile width x LDS capacity) over reps launches
- * on stream with HIP events and keep the fastest; writes it to *chosen when
- * non-NULL.  Outputs are recomputed, never changed.  Drops a captured graph. */
-int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, rbsm_tuning *chosen);
+/* Project autotuner.  Times candidate tunings over reps launches each on
+ * stream with HIP events and keeps the fastest, searching one axis after the
+ * other: tile width x launch form (one workgroup per tile or persistent),
+ * then (one workgroup per tile) the XCD chunking, then LDS capacity, then
+ * apron, then (persistent) the walk blocking.  The
+ * choice is cached in the process under a key of the device (architecture,
+ * CU count) and the plan's job layout (per job: fragments, view width, map
+ * size and pitch, MAXDIST, mode); a later call with the same key applies the
+ * cached tuning without timing unless flags bit 0 (RBSM_TUNE_FORCE) is set.
+ * Writes the tuning to *chosen when non-NULL.  Outputs are recomputed, never
+ * changed.  Drops a captured graph. */
+enum { RBSM_TUNE_FORCE = 1 };
+int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_t flags, rbsm_tuning *chosen);
+
+/* The autotuner cache as a text file (one line per key: key tile_w apron
+ * lds_cap persistent walk_first walk_block xcd_chunk).  load returns the number of
+ * entries read (>= 0) or a negative code (unreadable file, malformed or
+ * invalid entry: entries before it stay loaded); save writes every entry. */
+int rbsm_tune_cache_load(const char *path);
+int rbsm_tune_cache_save(const char *path);
+void rbsm_tune_cache_clear(void);
 
 int rbsm_plan_set_tuning(rbsm_plan *plan, const rbsm_tuning *tune);  /* drops a captured graph */
 int rbsm_plan_get_tuning(const rbsm_plan *plan, rbsm_tuning *tune);
@@ -336,7 +365,8 @@ void rbsm_engine_destroy(rbsm_engine *engine);
 const char *rbsm_last_error(void);
 
 /* ABI version: 100 * major + minor (1.02: compositing, the serving engine and
- * rasterization). */
+ * rasterization; 1.03: persistent launches, walk blocking and the tuning
+ * cache). */
 int32_t rbsm_abi_version(void);
 
 #ifdef __cplusplus

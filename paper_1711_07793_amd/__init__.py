@@ -47,7 +47,15 @@ class Params:
 
 class RbsmTuning(ctypes.Structure):
     """Mirror of ``rbsm_tuning`` (include/rbsm.h)."""
-    _fields_ = [("tile_w", ctypes.c_int32), ("apron", ctypes.c_int32), ("lds_cap", ctypes.c_int32)]
+    _fields_ = [("tile_w", ctypes.c_int32), ("apron", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("walk_first", ctypes.c_int32), ("walk_block", ctypes.c_int32),
+                ("xcd_chunk", ctypes.c_int32)]
+
+    def __init__(self, tile_w=32, apron=1, lds_cap=2048, persistent=0, walk_first=0, walk_block=0, xcd_chunk=-1):
+        super().__init__(tile_w, apron, lds_cap, persistent, walk_first, walk_block, xcd_chunk)
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class RbsmJob(ctypes.Structure):
@@ -110,8 +118,14 @@ def load_library() -> ctypes.CDLL:
     lib.rbsm_plan_update.restype = ctypes.c_int
     lib.rbsm_plan_launch.argtypes = [vp, vp]
     lib.rbsm_plan_launch.restype = ctypes.c_int
-    lib.rbsm_plan_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(RbsmTuning)]
+    lib.rbsm_plan_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(RbsmTuning)]
     lib.rbsm_plan_autotune.restype = ctypes.c_int
+    lib.rbsm_tune_cache_load.argtypes = [ctypes.c_char_p]
+    lib.rbsm_tune_cache_load.restype = ctypes.c_int
+    lib.rbsm_tune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.rbsm_tune_cache_save.restype = ctypes.c_int
+    lib.rbsm_tune_cache_clear.argtypes = []
+    lib.rbsm_tune_cache_clear.restype = None
     lib.rbsm_plan_set_tuning.argtypes = [vp, ctypes.POINTER(RbsmTuning)]
     lib.rbsm_plan_set_tuning.restype = ctypes.c_int
     lib.rbsm_plan_get_tuning.argtypes = [vp, ctypes.POINTER(RbsmTuning)]
@@ -261,6 +275,23 @@ def rbsm_footprint(shadow_map: torch.Tensor, frags: torch.Tensor, params, mode: 
     return touched
 
 
+def tune_cache_load(path: str) -> int:
+    """Load autotuner choices from a text file; returns the entries read."""
+    lib = load_library()
+    st = lib.rbsm_tune_cache_load(os.fsencode(path))
+    if st < 0:
+        raise RbsmError(f"rbsm_tune_cache_load returned {st}: {rbsm_last_error()}")
+    return st
+
+
+def tune_cache_save(path: str) -> None:
+    _call("rbsm_tune_cache_save", os.fsencode(path))
+
+
+def tune_cache_clear() -> None:
+    load_library().rbsm_tune_cache_clear()
+
+
 class Plan:
     """Batched form: one launch (or graph replay) for many (view, light) jobs.
 
@@ -305,9 +336,11 @@ class Plan:
     def launch(self, stream=None):
         _call("rbsm_plan_launch", self._h, _stream(stream))
 
-    def autotune(self, reps: int = 5, stream=None) -> RbsmTuning:
+    def autotune(self, reps: int = 5, stream=None, force: bool = False) -> RbsmTuning:
+        """Run the project autotuner (or apply its cached choice for this
+        device and job layout unless ``force``)."""
         t = RbsmTuning()
-        _call("rbsm_plan_autotune", self._h, _stream(stream), int(reps), ctypes.byref(t))
+        _call("rbsm_plan_autotune", self._h, _stream(stream), int(reps), 1 if force else 0, ctypes.byref(t))
         return t
 
     @property
@@ -329,12 +362,16 @@ class Plan:
         return int(self._lib.rbsm_plan_fragments(self._h))
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            self._lib.rbsm_plan_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rbsm_plan_destroy(h)
+            self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
 
 
 PRIM_BYTES = 112  # sizeof(rbsm_prim)
@@ -475,14 +512,18 @@ class Engine:
         return {f: int(getattr(s, f)) for f, _ in RbsmEngineStats._fields_}
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
-            self._lib.rbsm_engine_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rbsm_engine_destroy(h)
+            self._h = None
         self._keep = {}
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: ctypes may already be gone
+            pass
 
 
-__all__ = ["Engine", "rbsm_rasterize", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+__all__ = ["tune_cache_load", "tune_cache_save", "tune_cache_clear", "Engine", "rbsm_rasterize", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
            "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

@@ -11,7 +11,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "rbsm.h"
@@ -171,6 +174,7 @@ struct rbsm_plan {
     JobDev *d_jobs = nullptr;
     uint16_t *d_block_job = nullptr;
     int64_t blocks = 0;
+    int64_t grid = 0;  // workgroups of a persistent launch (resident ones, at most blocks)
     int64_t fragments = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -191,6 +195,8 @@ void free_tables(rbsm_plan *p) {
     p->d_jobs = nullptr;
     p->d_block_job = nullptr;
 }
+
+int64_t plan_grid(const rbsm_plan *p);
 
 // Validate jobs and build (and upload) the device job table and the
 // block -> job map for the plan's tile width.
@@ -257,27 +263,108 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
     plan->jobs.assign(jobs, jobs + n_jobs);
     plan->blocks = base;
     plan->fragments = frags;
+    plan->grid = plan_grid(plan);
     return RBSM_OK;
+}
+
+// The batched kernel instance of a tuning: one workgroup per tile
+// (batch_kernel) or resident workgroups looping over tiles
+// (batch_persistent_kernel, built for every walk blocking the tuner tries).
+template <int TW>
+const void *persistent_instance(int wf, int wb) {
+    if (wb == 8) {
+        if (wf == 1) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 1, 8>);
+        if (wf == 4) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 4, 8>);
+        return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 2, 8>);
+    }
+    if (wf == 1) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 1, 4>);
+    if (wf == 4) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 4, 4>);
+    return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 2, 4>);
+}
+
+const void *batch_instance(const rbsm_tuning &t) {
+    const int wf = t.walk_first ? t.walk_first : kWalkFirst, wb = t.walk_block ? t.walk_block : kWalkSteps;
+    if (!t.persistent) {
+        if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_kernel<16>);
+        if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_kernel<64>);
+        return reinterpret_cast<const void *>(&batch_kernel<32>);
+    }
+    if (t.tile_w == 16) return persistent_instance<16>(wf, wb);
+    if (t.tile_w == 64) return persistent_instance<64>(wf, wb);
+    return persistent_instance<32>(wf, wb);
+}
+
+// Workgroups a launch of the plan's tuning uses.
+int64_t plan_grid(const rbsm_plan *p) {
+    if (!p->tune.persistent) return p->blocks;
+    const size_t lds = (size_t)p->tune.lds_cap * sizeof(float);
+    return std::min<int64_t>(p->blocks, resident_groups(batch_instance(p->tune), lds));
 }
 
 void launch_batch(const rbsm_plan *p, hipStream_t stream) {
     if (p->blocks == 0) return;
-    const dim3 grid((unsigned)p->blocks), block(kT);
     const size_t lds = (size_t)p->tune.lds_cap * sizeof(float);
-    switch (p->tune.tile_w) {
-        case 16:
-            hipLaunchKernelGGL(batch_kernel<16>, grid, block, lds, stream, p->d_jobs, p->d_block_job, p->tune.apron,
-                               p->tune.lds_cap);
-            break;
-        case 64:
-            hipLaunchKernelGGL(batch_kernel<64>, grid, block, lds, stream, p->d_jobs, p->d_block_job, p->tune.apron,
-                               p->tune.lds_cap);
-            break;
-        default:
-            hipLaunchKernelGGL(batch_kernel<32>, grid, block, lds, stream, p->d_jobs, p->d_block_job, p->tune.apron,
-                               p->tune.lds_cap);
-            break;
+    const void *k = batch_instance(p->tune);
+    const JobDev *jobs = p->d_jobs;
+    const uint16_t *bj = p->d_block_job;
+    int apron = p->tune.apron, cap = p->tune.lds_cap, chunk = p->tune.xcd_chunk;
+    int64_t tiles = p->blocks;
+    if (!p->tune.persistent) {
+        void *args[] = {(void *)&jobs, (void *)&bj, (void *)&apron, (void *)&cap, (void *)&chunk};
+        (void)hipLaunchKernel(k, dim3((unsigned)p->blocks), dim3(kT), args, lds, stream);
+    } else {
+        void *args[] = {(void *)&jobs, (void *)&bj, (void *)&tiles, (void *)&apron, (void *)&cap};
+        (void)hipLaunchKernel(k, dim3((unsigned)p->grid), dim3(kT), args, lds, stream);
     }
+}
+
+// Autotuner cache: the chosen tuning per (device, job mix).  The key names
+// the device (architecture and CU count) and hashes every job's layout
+// (fragment count, view width, map size and pitch, MAXDIST, mode) -- what
+// the kernels' speed depends on, not the data.
+std::mutex g_tune_mu;
+std::map<std::string, rbsm_tuning> g_tune_cache;
+
+std::string tune_key(const rbsm_plan *p) {
+    hipDeviceProp_t prop{};
+    char dev[96] = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess)
+        snprintf(dev, sizeof(dev), "%s-cu%d", prop.gcnArchName, prop.multiProcessorCount);
+    for (char *c = dev; *c; ++c)
+        if (*c == ' ' || *c == ':') *c = '_';
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the job layout
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix((int64_t)p->jobs.size());
+    for (const rbsm_job &J : p->jobs) {
+        mix(J.n);
+        mix(J.params.view_width);
+        mix(J.params.width);
+        mix(J.params.height);
+        mix(J.params.pitch);
+        mix(J.params.max_dist);
+        mix(J.mode);
+    }
+    char key[160];
+    snprintf(key, sizeof(key), "%s/%016llx", dev, (unsigned long long)h);
+    return key;
+}
+
+bool tune_cache_get(const std::string &key, rbsm_tuning *t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+void tune_cache_put(const std::string &key, const rbsm_tuning &t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = t;
 }
 
 }  // namespace
@@ -351,6 +438,10 @@ rbsm_tuning rbsm_default_tuning(void) {
     t.tile_w = kDefaultTile.tile_w;
     t.apron = kDefaultTile.apron;
     t.lds_cap = kDefaultTile.cap;
+    t.persistent = kDefaultTile.persistent;
+    t.walk_first = kWalkFirst;
+    t.walk_block = kWalkSteps;
+    t.xcd_chunk = kDefaultTile.chunk_log2;
     return t;
 }
 
@@ -358,11 +449,14 @@ int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, i
                     const rbsm_tuning *tune, void *out, hipStream_t stream) {
     if (mode != 0 && mode != 1) return fail(RBSM_ERR_INVALID_ARG, "rbsm_pass_tuned: mode must be 0 or 1");
     if (!tuning_ok(tune)) return fail(RBSM_ERR_INVALID_ARG, "rbsm_pass_tuned: invalid tuning");
+    if ((tune->walk_first != 0 && tune->walk_first != kWalkFirst) ||
+        (tune->walk_block != 0 && tune->walk_block != kWalkSteps))
+        return fail(RBSM_ERR_INVALID_ARG, "rbsm_pass_tuned: walk_first and walk_block must be 0 or the defaults");
     MapView mv;
     const int st = validate("rbsm_pass_tuned", shadow_map, frags, n, p, out, mode == 0 ? 1 : 4, false, &mv);
     if (st != RBSM_OK) return st;
     if (n == 0) return RBSM_OK;
-    const TileConfig cfg{tune->tile_w, tune->apron, tune->lds_cap};
+    const TileConfig cfg{tune->tile_w, tune->apron, tune->lds_cap, tune->persistent, tune->xcd_chunk};
     if (mode == 0)
         launch_pass<true>(mv, frags, n, p->view_width, p->depth_bias, p->max_dist, cfg, out, 4, stream);
     else
@@ -377,6 +471,8 @@ int rbsm_plan_create(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tu
     rbsm_plan *p = new (std::nothrow) rbsm_plan();
     if (!p) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_create: out of host memory");
     p->tune = tune ? *tune : rbsm_default_tuning();
+    if (!p->tune.walk_first) p->tune.walk_first = kWalkFirst;
+    if (!p->tune.walk_block) p->tune.walk_block = kWalkSteps;
     (void)hipGetDevice(&p->device);
     const int st = build_tables(p, jobs, n_jobs, false);
     if (st != RBSM_OK) {
@@ -407,17 +503,22 @@ int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream) {
 int rbsm_plan_set_tuning(rbsm_plan *plan, const rbsm_tuning *tune) {
     if (!plan || !tuning_ok(tune)) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_set_tuning: invalid argument");
     drop_graph(plan);
-    if (tune->tile_w != plan->tune.tile_w) {
+    rbsm_tuning t = *tune;
+    if (!t.walk_first) t.walk_first = kWalkFirst;
+    if (!t.walk_block) t.walk_block = kWalkSteps;
+    if (t.tile_w != plan->tune.tile_w) {
         const rbsm_tuning old = plan->tune;
-        plan->tune = *tune;
+        plan->tune = t;
         const std::vector<rbsm_job> jobs = plan->jobs;
         const int st = build_tables(plan, jobs.data(), (int32_t)jobs.size(), false);
         if (st != RBSM_OK) {
             plan->tune = old;
+            plan->grid = plan_grid(plan);
             return st;
         }
     }
-    plan->tune = *tune;
+    plan->tune = t;
+    plan->grid = plan_grid(plan);
     return RBSM_OK;
 }
 
@@ -427,44 +528,132 @@ int rbsm_plan_get_tuning(const rbsm_plan *plan, rbsm_tuning *tune) {
     return RBSM_OK;
 }
 
-int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, rbsm_tuning *chosen) {
-    if (!plan || reps < 1) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_autotune: invalid argument");
+int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_t flags, rbsm_tuning *chosen) {
+    if (!plan || reps < 1 || (flags & ~1) != 0) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_autotune: invalid argument");
     drop_graph(plan);
-    const int tws[] = {16, 32, 64};
-    const int caps[] = {2048, 3072, 4096};
+    const std::string key = tune_key(plan);
+    rbsm_tuning best = plan->tune;
+    if (!(flags & 1) && tune_cache_get(key, &best)) {
+        const int st = rbsm_plan_set_tuning(plan, &best);
+        if (st == RBSM_OK && chosen) *chosen = plan->tune;
+        return st;
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(RBSM_ERR_HIP, "rbsm_plan_autotune: could not create events");
-    rbsm_tuning best = plan->tune;
     float best_ms = 1e30f;
     int status = RBSM_OK;
-    for (int tw : tws) {
-        for (int cap : caps) {
-            rbsm_tuning cand{tw, 1, cap};
-            if ((status = rbsm_plan_set_tuning(plan, &cand)) != RBSM_OK) break;
-            launch_batch(plan, stream);  // warm-up
-            (void)hipEventRecord(e0, stream);
-            for (int r = 0; r < reps; ++r) launch_batch(plan, stream);
-            (void)hipEventRecord(e1, stream);
-            if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
-                status = fail(RBSM_ERR_HIP, "rbsm_plan_autotune: a timed launch failed");
-                break;
-            }
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = cand;
-            }
+    // time one candidate: a warm-up launch, then reps launches between events
+    auto trial = [&](const rbsm_tuning &cand) {
+        if (status != RBSM_OK) return;
+        if ((status = rbsm_plan_set_tuning(plan, &cand)) != RBSM_OK) return;
+        launch_batch(plan, stream);
+        (void)hipEventRecord(e0, stream);
+        for (int r = 0; r < reps; ++r) launch_batch(plan, stream);
+        (void)hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+            status = fail(RBSM_ERR_HIP, "rbsm_plan_autotune: a timed launch failed");
+            return;
         }
-        if (status != RBSM_OK) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = plan->tune;
+        }
+    };
+    // coordinate search: tile shape and schedule, then (one workgroup per
+    // tile) how tiles are dealt to XCDs, then LDS capacity, then apron, then
+    // (persistent launches) the walk blocking
+    rbsm_tuning base = rbsm_default_tuning();
+    for (int tw : {16, 32, 64})
+        for (int per : {0, 1}) {
+            rbsm_tuning c = base;
+            c.tile_w = tw;
+            c.persistent = per;
+            trial(c);
+        }
+    base = best;
+    if (!base.persistent)
+        for (int chunk : {3, 5, 7}) {
+            rbsm_tuning c = base;
+            c.xcd_chunk = chunk;
+            trial(c);
+        }
+    base = best;
+    for (int cap : {1536, 3072, 4096}) {
+        rbsm_tuning c = base;
+        c.lds_cap = cap;
+        trial(c);
     }
+    base = best;
+    {
+        rbsm_tuning c = base;
+        c.apron = base.apron == 1 ? 2 : 1;
+        trial(c);
+    }
+    base = best;
+    if (base.persistent)
+        for (int wf : {1, 2, 4})
+            for (int wb : {4, 8}) {
+                if (wf == base.walk_first && wb == base.walk_block) continue;
+                rbsm_tuning c = base;
+                c.walk_first = wf;
+                c.walk_block = wb;
+                trial(c);
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != RBSM_OK) return status;
     if ((status = rbsm_plan_set_tuning(plan, &best)) != RBSM_OK) return status;
-    if (chosen) *chosen = best;
+    tune_cache_put(key, plan->tune);
+    if (chosen) *chosen = plan->tune;
     return RBSM_OK;
+}
+
+int rbsm_tune_cache_save(const char *path) {
+    if (!path) return fail(RBSM_ERR_INVALID_ARG, "rbsm_tune_cache_save: path is null");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(RBSM_ERR_INVALID_ARG, "rbsm_tune_cache_save: cannot open %s", path);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        fprintf(f, "# rbsm tuning cache v2: key tile_w apron lds_cap persistent walk_first walk_block xcd_chunk\n");
+        for (const auto &kv : g_tune_cache) {
+            const rbsm_tuning &t = kv.second;
+            fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), t.tile_w, t.apron, t.lds_cap, t.persistent,
+                    t.walk_first, t.walk_block, t.xcd_chunk);
+        }
+    }
+    const bool ok = fclose(f) == 0;
+    return ok ? RBSM_OK : fail(RBSM_ERR_INVALID_ARG, "rbsm_tune_cache_save: write failed for %s", path);
+}
+
+int rbsm_tune_cache_load(const char *path) {
+    if (!path) return fail(RBSM_ERR_INVALID_ARG, "rbsm_tune_cache_load: path is null");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(RBSM_ERR_INVALID_ARG, "rbsm_tune_cache_load: cannot open %s", path);
+    char line[512];
+    int loaded = 0, status = RBSM_OK;
+    while (fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char key[256];
+        rbsm_tuning t{};
+        if (sscanf(line, "%255s %d %d %d %d %d %d %d", key, &t.tile_w, &t.apron, &t.lds_cap, &t.persistent,
+                   &t.walk_first, &t.walk_block, &t.xcd_chunk) != 8 ||
+            !tuning_ok(&t)) {
+            status = fail(RBSM_ERR_INVALID_ARG, "rbsm_tune_cache_load: malformed entry in %s", path);
+            break;
+        }
+        tune_cache_put(key, t);
+        ++loaded;
+    }
+    fclose(f);
+    return status == RBSM_OK ? loaded : status;
+}
+
+void rbsm_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
 }
 
 int rbsm_plan_capture(rbsm_plan *plan, hipStream_t stream) {
@@ -715,6 +904,6 @@ void rbsm_engine_destroy(rbsm_engine *E) {
 
 const char *rbsm_last_error(void) { return g_err; }
 
-int32_t rbsm_abi_version(void) { return 102; }
+int32_t rbsm_abi_version(void) { return 103; }
 
 }  // extern "C"

@@ -21,11 +21,37 @@ struct MapView {
     int W, H;
 };
 
+// Loads and stores of device buffers through global-address-space pointers:
+// pointers read from a job table in memory are otherwise generic, and the
+// compiler then emits flat instructions, which count against the LDS counter
+// too, so every LDS wait also waits for memory (and back-to-back loads of one
+// fragment were serialised).
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+// 16-byte forms through a native vector type (HIP's float4 is a class whose
+// copy takes a generic reference, which would bring the flat access back).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 gld4(const float4 *p) {
+    const f32x4 v = *(const __attribute__((address_space(1))) f32x4 *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst4(float4 *p, float4 v) {
+    f32x4 w;
+    w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+    *(__attribute__((address_space(1))) f32x4 *)p = w;
+}
+
 // Nearest-texel fetch with clamp-to-edge.
 __device__ __forceinline__ float texel(const MapView &m, int i, int j) {
     i = min(max(i, 0), m.W - 1);
     j = min(max(j, 0), m.H - 1);
-    return m.t[(int64_t)j * m.pitch + i];
+    return gld(m.t + ((int64_t)j * m.pitch + i));
 }
 
 // Eq. 1: lit (1) unless the biased fragment depth lies behind the blocker.

@@ -44,6 +44,7 @@ constexpr int kServeSlots = 2;       // steps whose compute may be pending
 constexpr int kArgJobs = 40;         // tile jobs per launch, passed in the kernel arguments
 constexpr int kArgComp = 20;         // composites per launch, passed in the kernel arguments
 constexpr int kServeTileW = 64;      // tile width of the merged jobs (as in the batched autotuner's choice)
+constexpr int kServeChunkLog2 = 5;   // merged jobs' tiles dealt to XCDs in chunks of 32 (balances XCDs)
 
 // One view's composite: out[k] = sum_l w[l] * vis_l[k].
 struct CompJob {
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                                                                                               int apron, int cap) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
-    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, kServeChunkLog2);
     const int j = find_job(a.first, a.n_jobs, g);
     const JobDev &J = a.jobs[j];
     process_tile<2, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,

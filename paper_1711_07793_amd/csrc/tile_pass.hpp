@@ -1,11 +1,16 @@
 // Main hard / RSMSS (radius 0) pass for gfx950: 2-D screen tiles whose
 // light-space footprint is staged in LDS, edge fragments compacted with wave
 // ballots, traversals run one lane per (edge fragment, direction) in blocks
-// of steps read from global memory.  Included once, by rbsm.hip.
+// of steps read from global memory.  A launch either gives every tile its own
+// workgroup or keeps only resident workgroups, each looping over tiles with
+// the next tile's fragments loading while it works on the current one.
+// Included once, by rbsm.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "rbsm.h"
 #include "rbsm_device.hpp"
@@ -22,6 +27,22 @@ __device__ __forceinline__ int64_t xcd_block(int b, int nb) {
                    : (int64_t)rem * (per + 1) + (int64_t)(x - rem) * per + local;
 }
 
+// Chunked XCD order: the launch's tiles are dealt to the 8 XCDs in chunks of
+// 2^chunk_log2 consecutive tiles, round-robin, so every XCD gets a share of
+// every part of the launch (a tile's cost varies several-fold between jobs:
+// staged or not, edges or not), while the tiles of a chunk still share one
+// L2.  chunk_log2 < 0: one contiguous range per XCD (xcd_block).  A bijection
+// for any grid size: the last, partial round of chunks is split contiguously.
+__device__ __forceinline__ int64_t xcd_chunked(int b, int nb, int chunk_log2) {
+    if (chunk_log2 < 0) return xcd_block(b, nb);
+    const int round = 8 << chunk_log2;
+    const int full = nb / round;
+    if (b >= full * round) return (int64_t)full * round + xcd_block(b - full * round, nb - full * round);
+    const int x = b & 7, l = b >> 3;
+    const int q = l >> chunk_log2, r = l & ((1 << chunk_log2) - 1);
+    return ((int64_t)(q * 8 + x) << chunk_log2) + r;
+}
+
 // ---------------------------------------------------------------------------
 // Main pass: 2-D screen tiles with their light-space footprint staged in LDS.
 // ---------------------------------------------------------------------------
@@ -30,15 +51,17 @@ constexpr int kT = 256;            // threads per workgroup
 constexpr int kF = 4;              // consecutive pixels per thread
 constexpr int kTileF = kT * kF;    // fragments per tile
 constexpr int kState = 128;        // edge fragments whose full state is kept in LDS
-constexpr int kWalkFirst = 2;     // steps every walk takes before the unfinished ones are compacted
-constexpr int kWalkSteps = 4;     // steps per block of a continued walk, all reads issued together
+constexpr int kWalkFirst = 2;     // default: steps every walk takes before the unfinished ones are compacted
+constexpr int kWalkSteps = 4;     // default: steps per block of a continued walk, all reads issued together
 constexpr int kCont = 512;         // continued walks queued per tile (more finish where they are)
 
-// Staged light-space footprint of one screen tile: texels [by0..by1] x
-// [bx0..bx1] of the map (clamped coordinates), row-major with stride bw.
+// Staged light-space footprint of one screen tile: the window of texels
+// [bx0, bx0+bw) x [by0, by0+bh) around the tile's (clamped) fragment texels,
+// grown by the apron even past the map's edge (clamped texels there), stored
+// row-major with stride bw.
 struct Staged {
     const float *lds;
-    int bx0, by0, bx1, by1, bw;
+    int bx0, by0, bw, bh;  // window origin (may be -apron) and size
     bool on;
 };
 
@@ -48,26 +71,53 @@ typedef __attribute__((address_space(3))) float lds_float;  // a float in LDS
 
 constexpr int kStageChunk = 8;  // texels per thread whose loads are in flight together
 
-// Copy texels [y0, y0+h) x [x0, x0+w) of the map into dst (row-major, stride
-// w), the workgroup's kT threads striding over the rectangle.  Each thread
-// issues kStageChunk loads before its first LDS store, so a chunk of
-// kT * kStageChunk texels costs one memory round trip, not one per texel.
+// Copy the map window [x0, x0+w) x [y0, y0+h) into dst (row-major, stride w).
+// The window may leave the map by the apron; positions outside it hold the
+// clamped texel, so a staged texel's 4 neighbours are always at fixed offsets
+// (+-1, +-w) with clamp-to-edge already applied.  Each thread issues
+// kStageChunk loads before its first LDS store, so a chunk costs one memory
+// round trip.
+//  - a window inside a map under 4 GiB and at most kT texels wide: every
+//    thread owns one column and kT / w rows per round; a texel costs a
+//    32-bit address add, a row compare and an LDS address add;
+//  - otherwise the threads stride over the window with clamped coordinates.
 __device__ __forceinline__ void stage_rect(const MapView &m, float *dst, int x0, int y0, int w, int h, int t) {
+    const bool inside = x0 >= 0 && y0 >= 0 && x0 + w <= m.W && y0 + h <= m.H;
+    if (inside && w <= kT && (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u)) {
+        const int rpi = kT / w;  // rows per round
+        const int c = t % w, r0 = t / w;
+        if (r0 >= rpi) return;   // the kT % w threads without a column
+        const char *base8 = (const char *)m.t;
+        const unsigned pitch4 = 4u * (unsigned)m.pitch;
+        const unsigned dstep = (unsigned)rpi * pitch4;
+        const int lstep = rpi * w;
+        unsigned off = (unsigned)(y0 + r0) * pitch4 + 4u * (unsigned)(x0 + c);
+        int li = r0 * w + c;
+        for (int r = r0; r < h; r += rpi * kStageChunk) {
+            float v[kStageChunk];
+#pragma unroll
+            for (int u = 0; u < kStageChunk; ++u) {
+                // rows past the window re-read the first row (in bounds) and are not stored
+                const bool ok = r + u * rpi < h;
+                v[u] = gld((const float *)(base8 + (ok ? off + (unsigned)u * dstep : off)));
+            }
+#pragma unroll
+            for (int u = 0; u < kStageChunk; ++u)
+                if (r + u * rpi < h) dst[li + u * lstep] = v[u];
+            off += (unsigned)kStageChunk * dstep;
+            li += kStageChunk * lstep;
+        }
+        return;
+    }
     const int area = w * h;
-    int r = t / w, c = t % w;
-    const int dr = kT / w, dc = kT % w;
     for (int base = 0; base < area; base += kT * kStageChunk) {
         float v[kStageChunk];
 #pragma unroll
         for (int u = 0; u < kStageChunk; ++u) {
-            const int idx = base + u * kT + t;
-            v[u] = idx < area ? m.t[(int64_t)(y0 + r) * m.pitch + (x0 + c)] : 0.0f;
-            r += dr;
-            c += dc;
-            if (c >= w) {
-                c -= w;
-                ++r;
-            }
+            const int idx = min(base + u * kT + t, area - 1);
+            const int r = idx / w, c = idx - r * w;
+            const int x = min(max(x0 + c, 0), m.W - 1), y = min(max(y0 + r, 0), m.H - 1);
+            v[u] = gld(m.t + ((int64_t)y * m.pitch + x));
         }
 #pragma unroll
         for (int u = 0; u < kStageChunk; ++u) {
@@ -90,9 +140,9 @@ struct GlobalWalkReader {  // a map under 4 GiB in global memory
     unsigned step4;          // bytes per unit of p
     __device__ __forceinline__ void operator()(int p, float &tc, float &ta, float &tb) const {
         const unsigned x = (unsigned)p * step4;
-        tc = *(const float *)(t + (c + x));
-        ta = *(const float *)(t + (a + x));
-        tb = *(const float *)(t + (b + x));
+        tc = gld((const float *)(t + (c + x)));
+        ta = gld((const float *)(t + (a + x)));
+        tb = gld((const float *)(t + (b + x)));
     }
 };
 
@@ -140,30 +190,106 @@ struct TileShared {
     int count, ncont;
 };
 
-// One workgroup owns a TW x (1024/TW) pixel tile of a row-major image of
-// width vw (flat mode: vw = n, TW = 1024); each thread owns 4 consecutive
-// pixels of one row (one 48-byte fragment load, one packed store).
-//  1. load fragments; the workgroup reduces the bounding box of their texels,
-//     grows it by `apron` texels and, when it holds at most `cap` texels,
-//     copies it into LDS with row-contiguous loads (else reads stay global);
+// Minimum over the 64 lanes of a wave, returned to every lane: a DPP
+// reduction (rows of 16 by shifts, then the row broadcasts), 6 VALU
+// instructions where a shuffle tree takes about 30.  The box reduction feeds
+// it values in [-1, 65535] or INT32_MAX, so negating one is safe.
+__device__ __forceinline__ int wave_min(int x) {
+    x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+// The thread index through an opaque copy: in a persistent loop nothing
+// derived from it is hoisted out of a tile and held in registers across tiles
+// (recomputing it per tile costs a few instructions; holding it costs VGPRs
+// the tile needs).
+__device__ __forceinline__ int opaque_tid() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+
+// Where a thread's 4 pixels of tile `tile_id` sit: a TW x (1024/TW) tile of a
+// row-major image of width vw (flat mode: vw = n, TW = 1024), each thread 4
+// consecutive pixels of one row.  Tile and image counts stay below 2^31.
+template <int TW>
+struct TilePos {
+    int64_t tyi, txi, px0, k0;
+    int avail;  // how many of the thread's 4 pixels are in the image (0..4)
+    __device__ __forceinline__ TilePos(int64_t vw, int64_t n, int64_t tiles_x, int64_t tile_id, int t) {
+        constexpr int TH = kTileF / TW;
+        constexpr int LPR = TW / kF;
+        tyi = (int64_t)((uint32_t)tile_id / (uint32_t)tiles_x);
+        txi = tile_id - tyi * tiles_x;
+        px0 = txi * TW + (int64_t)(t % LPR) * kF;
+        k0 = (tyi * TH + t / LPR) * vw + px0;
+        const int64_t lim = min(vw - px0, n - k0);
+        avail = (int)max(min(lim, (int64_t)kF), (int64_t)0);
+    }
+};
+
+// Fragment loads of one thread for one tile: one 48-byte load (three 16-byte
+// ones) when the 4 pixels are in range and aligned, else guarded 4-byte loads
+// (zeros where a pixel lies outside the image).
+template <int TW>
+__device__ __forceinline__ void load_tile_frags(const float *__restrict__ frags, int64_t n, int64_t vw,
+                                                int64_t tiles_x, int64_t tile_id, int vec_ok, float (&fr)[3 * kF]) {
+    const TilePos<TW> P(vw, n, tiles_x, tile_id, opaque_tid());
+    bool valid[kF];
+#pragma unroll
+    for (int f = 0; f < kF; ++f) valid[f] = f < P.avail;
+    if (vec_ok && valid[kF - 1]) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(frags + 3 * P.k0);
+        const float4 a = gld4(p4), b = gld4(p4 + 1), c = gld4(p4 + 2);
+        fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
+        fr[4] = b.x; fr[5] = b.y; fr[6] = b.z; fr[7] = b.w;
+        fr[8] = c.x; fr[9] = c.y; fr[10] = c.z; fr[11] = c.w;
+    } else {
+#pragma unroll
+        for (int f = 0; f < kF; ++f) {
+            const int64_t k = P.k0 + f;
+            fr[3 * f + 0] = valid[f] ? gld(frags + 3 * k + 0) : 0.0f;
+            fr[3 * f + 1] = valid[f] ? gld(frags + 3 * k + 1) : 0.0f;
+            fr[3 * f + 2] = valid[f] ? gld(frags + 3 * k + 2) : 0.0f;
+        }
+    }
+}
+
+struct NoPrefetch {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// One tile whose fragments fr the thread has already loaded:
+//  1. the workgroup reduces the bounding box of the fragments' texels, grows
+//     it by `apron` texels and, when it holds at most `cap` texels, copies it
+//     into LDS with row-contiguous loads (else reads stay global);
 //  2. centre and neighbour tests; fragments without a discontinuity (and, in
 //     hard mode, shadowed ones) are final and stored at once;
 //  3. edge fragments are compacted with wave ballots into an LDS queue that
 //     keeps their texel, depth, sub-texel position, test and mask;
-//  4. one lane per (edge fragment, direction) takes the walk's first
-//     kWalkFirst steps from global memory (L2); walks still running are
-//     queued again and continued in blocks of kWalkSteps steps;
+//  4. one lane per (edge fragment, direction) takes the walk's first WF
+//     steps from global memory (L2); walks still running are queued again
+//     and continued in blocks of WB steps;
 //  5. one lane per edge fragment normalizes, evaluates the visibility
 //     function and stores.
-// Staging, tile shape and queues only decide where texels are read from and
-// by which lane: every result equals the per-fragment listing.
+// `prefetch` runs once, right after the box reduction, every thread of the
+// workgroup calling it: the persistent kernels issue the next tile's fragment
+// loads there, so they arrive while this tile is staged, tested and walked.
+// Staging, tile shape, queues and walk blocking only decide where texels are
+// read from and by which lane: every result equals the per-fragment listing.
 // MODE: 1 hard pass, 0 RSMSS, 2 either, chosen per call by hard_rt (one code
 // path for workgroups of both modes in one launch).
-template <int MODE, int TW>
-__device__ __forceinline__ void process_tile(MapView m, const float *__restrict__ frags, int64_t n, int64_t vw,
-                                             int64_t tiles_x, float bias, int maxd, int apron, int cap,
-                                             int vec_ok, void *__restrict__ out_v, int64_t tile_id,
-                                             TileShared &sh, float *s_tex, bool hard_rt = false) {
+template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class Prefetch = NoPrefetch>
+__device__ __forceinline__ void process_tile_loaded(MapView m, const float *__restrict__ frags, int64_t n,
+                                                    int64_t vw, int64_t tiles_x, float bias, int maxd, int apron,
+                                                    int cap, int vec_ok, void *__restrict__ out_v, int64_t tile_id,
+                                                    const float (&fr)[3 * kF], TileShared &sh, float *s_tex,
+                                                    bool hard_rt, const Prefetch &prefetch) {
     const bool HARD = MODE == 2 ? hard_rt : MODE == 1;
     constexpr int TH = kTileF / TW;
     constexpr int LPR = TW / kF;
@@ -178,39 +304,22 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
     auto &q_rd = sh.rd;
     int &q_count = sh.count;
 
-    const int t = threadIdx.x;
+    const int t = opaque_tid();
     const int lane = t & 63, wave = t >> 6;
-    const int64_t tyi = tile_id / tiles_x, txi = tile_id % tiles_x;
-    const int64_t px0 = txi * TW + (int64_t)(t % LPR) * kF;
-    const int64_t k0 = (tyi * TH + t / LPR) * vw + px0;
+    const TilePos<TW> P(vw, n, tiles_x, tile_id, t);
+    const int64_t tyi = P.tyi, txi = P.txi, k0 = P.k0;
     const unsigned long long below = __lanemask_lt();
 
     Staged st;
     {
         bool valid[kF];
 #pragma unroll
-        for (int f = 0; f < kF; ++f) valid[f] = (px0 + f < vw) && (k0 + f < n);
+        for (int f = 0; f < kF; ++f) valid[f] = f < P.avail;
         const bool full = vec_ok && valid[kF - 1];
 
-        float fr[3 * kF];
-        if (full) {
-            const float4 *p4 = reinterpret_cast<const float4 *>(frags + 3 * k0);
-            const float4 a = p4[0], b = p4[1], c = p4[2];
-            fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
-            fr[4] = b.x; fr[5] = b.y; fr[6] = b.z; fr[7] = b.w;
-            fr[8] = c.x; fr[9] = c.y; fr[10] = c.z; fr[11] = c.w;
-        } else {
-#pragma unroll
-            for (int f = 0; f < kF; ++f) {
-                const int64_t k = k0 + f;
-                fr[3 * f + 0] = valid[f] ? frags[3 * k + 0] : 0.0f;
-                fr[3 * f + 1] = valid[f] ? frags[3 * k + 1] : 0.0f;
-                fr[3 * f + 2] = valid[f] ? frags[3 * k + 2] : 0.0f;
-            }
-        }
-
         Addr ad[kF];
-        int imin = INT32_MAX, imax = INT32_MIN, jmin = INT32_MAX, jmax = INT32_MIN;
+        // clamped texel indices lie in [0, 65535]: -1 marks "no fragment"
+        int imin = INT32_MAX, imax = -1, jmin = INT32_MAX, jmax = -1;
 #pragma unroll
         for (int f = 0; f < kF; ++f) {
             ad[f] = address(fr[3 * f], fr[3 * f + 1], fr[3 * f + 2], m.W, m.H, bias);
@@ -220,13 +329,10 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
                 jmin = min(jmin, jc); jmax = max(jmax, jc);
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            imin = min(imin, __shfl_xor(imin, off));
-            imax = max(imax, __shfl_xor(imax, off));
-            jmin = min(jmin, __shfl_xor(jmin, off));
-            jmax = max(jmax, __shfl_xor(jmax, off));
-        }
+        imin = wave_min(imin);
+        imax = -wave_min(-imax);
+        jmin = wave_min(jmin);
+        jmax = -wave_min(-jmax);
         if (lane == 0) {
             s_box[wave][0] = imin; s_box[wave][1] = imax;
             s_box[wave][2] = jmin; s_box[wave][3] = jmax;
@@ -236,20 +342,19 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
             sh.ncont = 0;
         }
         __syncthreads();
+        prefetch();
 #pragma unroll
         for (int w = 0; w < kT / 64; ++w) {
             imin = min(imin, s_box[w][0]); imax = max(imax, s_box[w][1]);
             jmin = min(jmin, s_box[w][2]); jmax = max(jmax, s_box[w][3]);
         }
         st.lds = s_tex;
-        st.bx0 = max(imin - apron, 0);
-        st.bx1 = min(imax + apron, m.W - 1);
-        st.by0 = max(jmin - apron, 0);
-        st.by1 = min(jmax + apron, m.H - 1);
-        st.bw = st.bx1 - st.bx0 + 1;
-        const int bh = st.by1 - st.by0 + 1;
-        st.on = imin <= imax && (int64_t)st.bw * bh <= (int64_t)cap;
-        if (st.on) stage_rect(m, s_tex, st.bx0, st.by0, st.bw, bh, t);
+        st.bx0 = imin - apron;
+        st.by0 = jmin - apron;
+        st.bw = imax - imin + 1 + 2 * apron;
+        st.bh = jmax - jmin + 1 + 2 * apron;
+        st.on = imin <= imax && (int64_t)st.bw * st.bh <= (int64_t)cap;
+        if (st.on) stage_rect(m, s_tex, st.bx0, st.by0, st.bw, st.bh, t);
         __syncthreads();
 
         // centre and neighbour texels; the staged path reads through an LDS
@@ -257,33 +362,43 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
         // pointer would make every read a 64-bit-addressed flat load)
         float tc[kF][5];  // left, centre, right, top, bottom
         if (st.on) {
+            // the window holds every fragment texel with a ring of at least
+            // one texel, clamped at the map's edge: neighbours at +-1, +-bw
             const lds_float *lt = (const lds_float *)s_tex;
 #pragma unroll
             for (int f = 0; f < kF; ++f) {
                 const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
-                const int il = max(ti - 1, 0), ir = min(ti + 1, m.W - 1);
-                const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
-                const int rc = (tj - st.by0) * st.bw - st.bx0;
-                const bool ok = valid[f];
-                tc[f][0] = ok ? lt[rc + il] : 0.0f;
-                tc[f][1] = ok ? lt[rc + ti] : 0.0f;
-                tc[f][2] = ok ? lt[rc + ir] : 0.0f;
-                tc[f][3] = ok ? lt[(jh - st.by0) * st.bw - st.bx0 + ti] : 0.0f;
-                tc[f][4] = ok ? lt[(jl - st.by0) * st.bw - st.bx0 + ti] : 0.0f;
+                const int c = valid[f] ? (tj - st.by0) * st.bw + (ti - st.bx0) : st.bw + 1;
+                tc[f][0] = lt[c - 1];
+                tc[f][1] = lt[c];
+                tc[f][2] = lt[c + 1];
+                tc[f][3] = lt[c + st.bw];
+                tc[f][4] = lt[c - st.bw];
             }
         } else {
+            const bool off32 = (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u);
+            const char *base8 = (const char *)m.t;
+            const unsigned pitch4 = 4u * (unsigned)m.pitch;
 #pragma unroll
             for (int f = 0; f < kF; ++f) {
                 const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
                 const int il = max(ti - 1, 0), ir = min(ti + 1, m.W - 1);
                 const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
-                const float *row = m.t + (int64_t)tj * m.pitch;
-                const bool ok = valid[f];
-                tc[f][0] = ok ? row[il] : 0.0f;
-                tc[f][1] = ok ? row[ti] : 0.0f;
-                tc[f][2] = ok ? row[ir] : 0.0f;
-                tc[f][3] = ok ? m.t[(int64_t)jh * m.pitch + ti] : 0.0f;
-                tc[f][4] = ok ? m.t[(int64_t)jl * m.pitch + ti] : 0.0f;
+                if (off32) {  // 32-bit byte offsets from the map's base
+                    const unsigned row = (unsigned)tj * pitch4;
+                    tc[f][0] = gld((const float *)(base8 + (row + 4u * (unsigned)il)));
+                    tc[f][1] = gld((const float *)(base8 + (row + 4u * (unsigned)ti)));
+                    tc[f][2] = gld((const float *)(base8 + (row + 4u * (unsigned)ir)));
+                    tc[f][3] = gld((const float *)(base8 + ((unsigned)jh * pitch4 + 4u * (unsigned)ti)));
+                    tc[f][4] = gld((const float *)(base8 + ((unsigned)jl * pitch4 + 4u * (unsigned)ti)));
+                } else {
+                    const float *row = m.t + (int64_t)tj * m.pitch;
+                    tc[f][0] = gld(row + il);
+                    tc[f][1] = gld(row + ti);
+                    tc[f][2] = gld(row + ir);
+                    tc[f][3] = gld(m.t + ((int64_t)jh * m.pitch + ti));
+                    tc[f][4] = gld(m.t + ((int64_t)jl * m.pitch + ti));
+                }
             }
         }
         bool s[kF], edge[kF];
@@ -305,21 +420,21 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
                 uint32_t packed = 0;
 #pragma unroll
                 for (int f = 0; f < kF; ++f) packed |= (uint32_t)(s[f] ? 1u : 0u) << (8 * f);
-                *reinterpret_cast<uint32_t *>(out + k0) = packed;
+                gst(reinterpret_cast<uint32_t *>(out + k0), packed);
             } else {
 #pragma unroll
                 for (int f = 0; f < kF; ++f)
-                    if (valid[f] && !edge[f]) out[k0 + f] = s[f] ? 1 : 0;
+                    if (valid[f] && !edge[f]) gst(out + k0 + f, (uint8_t)(s[f] ? 1 : 0));
             }
         } else {
             float *out = static_cast<float *>(out_v);
             if (full && !any_edge) {
-                *reinterpret_cast<float4 *>(out + k0) =
-                    make_float4(s[0] ? 1.0f : 0.0f, s[1] ? 1.0f : 0.0f, s[2] ? 1.0f : 0.0f, s[3] ? 1.0f : 0.0f);
+                gst4(reinterpret_cast<float4 *>(out + k0),
+                    make_float4(s[0] ? 1.0f : 0.0f, s[1] ? 1.0f : 0.0f, s[2] ? 1.0f : 0.0f, s[3] ? 1.0f : 0.0f));
             } else {
 #pragma unroll
                 for (int f = 0; f < kF; ++f)
-                    if (valid[f] && !edge[f]) out[k0 + f] = s[f] ? 1.0f : 0.0f;
+                    if (valid[f] && !edge[f]) gst(out + k0 + f, s[f] ? 1.0f : 0.0f);
             }
         }
 
@@ -369,7 +484,7 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
             i0 = q_i[e]; j0 = q_j[e]; zb = q_z[e]; fx = q_fx[e]; fy = q_fy[e];
         } else {
             const int64_t k = frag_of(e);
-            const Addr b = address(frags[3 * k], frags[3 * k + 1], frags[3 * k + 2], m.W, m.H, bias);
+            const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), gld(frags + 3 * k + 2), m.W, m.H, bias);
             i0 = b.i0; j0 = b.j0; zb = b.zb; fx = b.fx; fy = b.fy;
         }
     };
@@ -377,9 +492,9 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
     // walks, one lane per (fragment, direction), straight from global memory
     // (L2) in blocks of steps whose reads are issued together; staging the
     // walks' bands in LDS first measured slower.  Most walks stop within a
-    // few steps, so every walk first takes kWalkFirst steps; the unfinished
-    // ones are compacted into a queue and continued by as few waves as
-    // possible instead of holding every wave that has one of them.
+    // few steps, so every walk first takes WF steps; the unfinished ones are
+    // compacted into a queue and continued by as few waves as possible
+    // instead of holding every wave that has one of them.
     const bool map_32 = (int64_t)m.pitch * m.H * 4 <= (int64_t)0xFFFFFFFFu;  // byte offsets fit 32 bits
     struct Walk {
         GlobalWalkReader r;
@@ -416,18 +531,17 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
         w.r.step4 = horiz ? 4u : 4u * (unsigned)m.pitch;
         return w;
     };
-    const int first = min(kWalkFirst, maxd);
+    const int first = min(WF, maxd);
     for (int task = t; task < 4 * ne; task += kT) {
         int i0, j0;
         const Walk w = make_walk(task, i0, j0);
         int rd;
         if (map_32) {
-            rd = walk_range<kWalkFirst>(w.r, 1, first, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
+            rd = walk_range<WF>(w.r, 1, first, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
             if (rd == 0 && first < maxd) {
                 const int slot = atomicAdd(&sh.ncont, 1);
                 if (slot < kCont) sh.cont[slot] = (int16_t)task;  // continued below
-                else rd = walk_range<kWalkSteps>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a,
-                                                 w.chk_b);
+                else rd = walk_range<WB>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
                 if (slot < kCont) continue;
             }
             if (rd == 0) rd = -(maxd + 1);
@@ -462,8 +576,7 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
             const int task = sh.cont[c];
             int i0, j0;
             const Walk w = make_walk(task, i0, j0);
-            const int rd = walk_range<kWalkSteps>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a,
-                                                  w.chk_b);
+            const int rd = walk_range<WB>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
             q_rd[task >> 2][task & 3] = (int8_t)(rd != 0 ? rd : -(maxd + 1));
         }
         __syncthreads();
@@ -478,26 +591,25 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
         const Axis axx = normalize_axis(q_rd[e][0], q_rd[e][1], fx);
         const Axis axy = normalize_axis(q_rd[e][3], q_rd[e][2], fy);
         const int64_t k = frag_of(e);
-        if (HARD) static_cast<uint8_t *>(out_v)[k] = vis_hard(axx, axy) != 0.0f ? 1 : 0;
-        else static_cast<float *>(out_v)[k] = vis_rsmss(s, axx, axy);
+        if (HARD) gst(static_cast<uint8_t *>(out_v) + k, (uint8_t)(vis_hard(axx, axy) != 0.0f ? 1 : 0));
+        else gst(static_cast<float *>(out_v) + k, vis_rsmss(s, axx, axy));
     }
 }
 
-// 8 waves per SIMD: 64 VGPRs (no spills) and, with the default LDS capacity,
-// 19 KB of LDS let 8 workgroups share a CU, so a 1080p frame's 2,040 tiles
-// are all resident at once (one round, no second prologue).
-template <bool HARD, int TW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void tile_kernel(
-    MapView m, const float *__restrict__ frags, int64_t n, int64_t vw, int64_t tiles_x, float bias, int maxd,
-    int apron, int cap, int vec_ok, void *__restrict__ out_v) {
-    extern __shared__ float s_tex[];
-    __shared__ TileShared sh;
-    process_tile<HARD, TW>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v,
-                           xcd_block(blockIdx.x, gridDim.x), sh, s_tex);
+// A tile whose fragments are loaded first (one workgroup per tile).
+template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps>
+__device__ __forceinline__ void process_tile(MapView m, const float *__restrict__ frags, int64_t n, int64_t vw,
+                                             int64_t tiles_x, float bias, int maxd, int apron, int cap,
+                                             int vec_ok, void *__restrict__ out_v, int64_t tile_id,
+                                             TileShared &sh, float *s_tex, bool hard_rt = false) {
+    float fr[3 * kF];
+    load_tile_frags<TW>(frags, n, vw, tiles_x, tile_id, vec_ok, fr);
+    process_tile_loaded<MODE, TW, WF, WB>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v, tile_id,
+                                          fr, sh, s_tex, hard_rt, NoPrefetch{});
 }
 
-// One job of a batched launch: a (view, light) pass over its own map,
-// fragments and output, owning tiles [tile_base, tile_base + tiles).
+// One job of a launch: a (view, light) pass over its own map, fragments and
+// output, owning tiles [tile_base, tile_base + tiles) of the launch.
 struct JobDev {
     MapView m;
     const float *frags;
@@ -507,34 +619,148 @@ struct JobDev {
     int maxd, vec_ok, mode;  // mode 0 hard, 1 RSMSS
 };
 
+// Persistent loop: the workgroup takes tiles g, g + G, g + 2G, ... of the
+// launch (G = grid size, g its XCD-ordered index, so in every round each XCD
+// works on one contiguous range of tiles and shares their texels in its L2).
+// The next tile's job is read at the start of a tile and its fragments are
+// loaded during the current one's staging, tests and walks.  job_of(tile)
+// returns the tile's job (wave-uniform).
+template <int MODE, int TW, int WF, int WB, class JobOf>
+__device__ __forceinline__ void persistent_loop(const JobOf &job_of, int64_t tiles, int apron, int cap,
+                                                TileShared &sh, float *s_tex) {
+    const int64_t G = gridDim.x;
+    int64_t g = xcd_block(blockIdx.x, gridDim.x);
+    if (g >= tiles) return;
+    JobDev J = job_of(g);
+    float fr[3 * kF];
+    load_tile_frags<TW>(J.frags, J.n, J.vw, J.tiles_x, g - J.tile_base, J.vec_ok, fr);
+    for (;;) {
+        const int64_t gn = g + G;
+        const bool more = gn < tiles;
+        JobDev Jn = J;
+        if (more) Jn = job_of(gn);
+        float fn[3 * kF];
+        auto pf = [&]() {
+            if (more) load_tile_frags<TW>(Jn.frags, Jn.n, Jn.vw, Jn.tiles_x, gn - Jn.tile_base, Jn.vec_ok, fn);
+        };
+        process_tile_loaded<MODE, TW, WF, WB>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap,
+                                              J.vec_ok, J.out, g - J.tile_base, fr, sh, s_tex, J.mode == 0, pf);
+        if (!more) break;
+        g = gn;
+        J = Jn;
+#pragma unroll
+        for (int q = 0; q < 3 * kF; ++q) fr[q] = fn[q];
+    }
+}
+
+// 8 waves per SIMD: 64 VGPRs (no spills) and, with the default LDS capacity,
+// 19 KB of LDS let 8 workgroups share a CU, so a 1080p frame's 2,040 tiles
+// are all resident at once (one round, no second prologue).
+template <bool HARD, int TW>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void tile_kernel(
+    MapView m, const float *__restrict__ frags, int64_t n, int64_t vw, int64_t tiles_x, float bias, int maxd,
+    int apron, int cap, int vec_ok, void *__restrict__ out_v, int chunk_log2) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    process_tile<HARD, TW>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v,
+                           xcd_chunked(blockIdx.x, gridDim.x, chunk_log2), sh, s_tex);
+}
+
+// The same pass with resident workgroups looping over the tiles (the job is
+// the kernel argument; tile_base 0).  The prefetched fragments take 12 more
+// VGPRs, so the kernel runs at up to 80 (6 waves per SIMD).
+template <bool HARD, int TW>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(6, 6))) void tile_persistent_kernel(
+    const JobDev J, int64_t tiles, int apron, int cap) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    persistent_loop<HARD, TW, kWalkFirst, kWalkSteps>([&](int64_t) { return J; }, tiles, apron, cap, sh, s_tex);
+}
+
 // Batched pass: one workgroup per tile of any job; block_job maps the
 // (XCD-ordered) workgroup index to its job.  Each tile runs the steps of the
 // single-view pass, so every output is bitwise the same; the mode is a
 // per-workgroup value, so one code path serves both and fits 64 VGPRs.
 template <int TW>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_kernel(const JobDev *__restrict__ jobs,
-                                                   const uint16_t *__restrict__ block_job, int apron, int cap) {
+                                                   const uint16_t *__restrict__ block_job, int apron, int cap,
+                                                   int chunk_log2) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
-    const int64_t g = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, chunk_log2);
     const JobDev J = jobs[block_job[g]];
     const int64_t tile = g - J.tile_base;
     process_tile<2, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out, tile, sh,
                         s_tex, J.mode == 0);
 }
 
+// Batched pass with resident workgroups looping over the tiles of every job,
+// the next tile's job and fragments read while the current tile is worked on;
+// WF and WB are the walk blocking the autotuner searches.
+template <int TW, int WF, int WB>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(6, 6))) void batch_persistent_kernel(
+    const JobDev *__restrict__ jobs, const uint16_t *__restrict__ block_job, int64_t tiles, int apron, int cap) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    persistent_loop<2, TW, WF, WB>([&](int64_t g) { return jobs[block_job[g]]; }, tiles, apron, cap, sh, s_tex);
+}
+
 // Launch configuration of the main pass (defaults of the plain entry points).
 struct TileConfig {
-    int tile_w;   // 16, 32, 64 (2-D tiles) or 1024 (flat)
-    int apron;    // texels staged beyond the fragments' texel box, >= 1
-    int cap;      // LDS texel capacity per workgroup
+    int tile_w;      // 16, 32, 64 (2-D tiles) or 1024 (flat)
+    int apron;       // texels staged beyond the fragments' texel box, >= 1
+    int cap;         // LDS texel capacity per workgroup
+    int persistent;  // 0: one workgroup per tile, 1: resident workgroups loop over tiles
+    int chunk_log2;  // tiles dealt to XCDs in chunks of 2^chunk_log2; < 0: contiguous ranges
 };
 
-constexpr TileConfig kDefaultTile{32, 1, 2048};
+constexpr TileConfig kDefaultTile{32, 1, 2048, 0, -1};
+constexpr int kMaxChunkLog2 = 12;
 
 inline bool tuning_ok(const rbsm_tuning *t) {
     return t && (t->tile_w == 16 || t->tile_w == 32 || t->tile_w == 64) && t->apron >= 1 && t->apron <= 8 &&
-           t->lds_cap >= 256 && t->lds_cap <= 12288;
+           t->lds_cap >= 256 && t->lds_cap <= 12288 && (t->persistent == 0 || t->persistent == 1) &&
+           (t->walk_first == 0 || t->walk_first == 1 || t->walk_first == 2 || t->walk_first == 4) &&
+           (t->walk_block == 0 || t->walk_block == 4 || t->walk_block == 8) && t->xcd_chunk >= -1 &&
+           t->xcd_chunk <= kMaxChunkLog2;
+}
+
+// Resident workgroups of a persistent launch: the occupancy of `kernel` at
+// `lds` bytes of dynamic LDS times the CUs of the current device.
+inline int64_t resident_groups(const void *kernel, size_t lds) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kT, lds) != hipSuccess || per < 1) per = 1;
+    return (int64_t)per * cus;
+}
+
+template <bool HARD, int TW>
+void launch_tiles(const MapView &mv, const float *frags, int64_t n, int64_t vw, int64_t tiles_x, int64_t tiles,
+                  float bias, int maxd, TileConfig cfg, int vec, void *out, hipStream_t stream) {
+    const size_t lds = (size_t)cfg.cap * sizeof(float);
+    if (cfg.persistent) {
+        JobDev J{};
+        J.m = mv;
+        J.frags = frags;
+        J.out = out;
+        J.n = n;
+        J.vw = vw;
+        J.tiles_x = tiles_x;
+        J.tile_base = 0;
+        J.bias = bias;
+        J.maxd = maxd;
+        J.vec_ok = vec;
+        J.mode = HARD ? 0 : 1;
+        const void *k = reinterpret_cast<const void *>(&tile_persistent_kernel<HARD, TW>);
+        const int64_t grid = std::min<int64_t>(tiles, resident_groups(k, lds));
+        hipLaunchKernelGGL((tile_persistent_kernel<HARD, TW>), dim3((unsigned)grid), dim3(kT), lds, stream, J, tiles,
+                           cfg.apron, cfg.cap);
+    } else {
+        hipLaunchKernelGGL((tile_kernel<HARD, TW>), dim3((unsigned)tiles), dim3(kT), lds, stream, mv, frags, n, vw,
+                           tiles_x, bias, maxd, cfg.apron, cfg.cap, vec, out, cfg.chunk_log2);
+    }
 }
 
 template <bool HARD>
@@ -551,25 +777,11 @@ void launch_pass(const MapView &mv, const float *frags, int64_t n, int64_t view_
     const int64_t tiles_x = (vw + tw - 1) / tw;
     const int64_t tiles = tiles_x * ((rows + th - 1) / th);
     const int vec = ((uintptr_t)frags % 16 == 0) && ((uintptr_t)out % out_align == 0) && (vw % 4 == 0);
-    const size_t lds = (size_t)cfg.cap * sizeof(float);
-    const dim3 grid((unsigned)tiles), block(kT);
     switch (tw) {
-        case 16:
-            hipLaunchKernelGGL((tile_kernel<HARD, 16>), grid, block, lds, stream, mv, frags, n, vw, tiles_x, bias,
-                               maxd, cfg.apron, cfg.cap, vec, out);
-            break;
-        case 64:
-            hipLaunchKernelGGL((tile_kernel<HARD, 64>), grid, block, lds, stream, mv, frags, n, vw, tiles_x, bias,
-                               maxd, cfg.apron, cfg.cap, vec, out);
-            break;
-        case 1024:
-            hipLaunchKernelGGL((tile_kernel<HARD, 1024>), grid, block, lds, stream, mv, frags, n, vw, tiles_x,
-                               bias, maxd, cfg.apron, cfg.cap, vec, out);
-            break;
-        default:
-            hipLaunchKernelGGL((tile_kernel<HARD, 32>), grid, block, lds, stream, mv, frags, n, vw, tiles_x, bias,
-                               maxd, cfg.apron, cfg.cap, vec, out);
-            break;
+        case 16: launch_tiles<HARD, 16>(mv, frags, n, vw, tiles_x, tiles, bias, maxd, cfg, vec, out, stream); break;
+        case 64: launch_tiles<HARD, 64>(mv, frags, n, vw, tiles_x, tiles, bias, maxd, cfg, vec, out, stream); break;
+        case 1024: launch_tiles<HARD, 1024>(mv, frags, n, vw, tiles_x, tiles, bias, maxd, cfg, vec, out, stream); break;
+        default: launch_tiles<HARD, 32>(mv, frags, n, vw, tiles_x, tiles, bias, maxd, cfg, vec, out, stream); break;
     }
 }
 

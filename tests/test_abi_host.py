@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.rbsm_abi_version() == 102
+    assert lib.rbsm_abi_version() == 103
 
 
 def _p(**kw):
@@ -95,7 +95,10 @@ def test_tuning_validated_on_host(lib):
     d = lib.rbsm_default_tuning()
     assert d.tile_w in (16, 32, 64) and d.apron >= 1 and d.lds_cap >= 256
     p = _p()
-    for bad in (rb.RbsmTuning(24, 1, 4096), rb.RbsmTuning(32, 0, 4096), rb.RbsmTuning(32, 1, 100000)):
+    for bad in (rb.RbsmTuning(24, 1, 4096), rb.RbsmTuning(32, 0, 4096), rb.RbsmTuning(32, 1, 100000),
+                rb.RbsmTuning(32, 1, 2048, 2, 0, 0), rb.RbsmTuning(32, 1, 2048, 0, 3, 0),
+                rb.RbsmTuning(32, 1, 2048, 0, 0, 5), rb.RbsmTuning(32, 1, 2048, 1, 4, 8),
+                rb.RbsmTuning(32, 1, 2048, 0, 0, 0, 13), rb.RbsmTuning(32, 1, 2048, 0, 0, 0, -2)):
         assert lib.rbsm_pass_tuned(0, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(bad), 0x200000, None) == -1
     assert lib.rbsm_pass_tuned(3, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(d), 0x200000, None) == -1
 
@@ -165,3 +168,37 @@ def test_rasterize_validated_on_host(lib):
     assert call(args(prims=0)) == -1
     assert call(args(out=0x100000 + 64)) == -1             # map over the primitive records
     assert "overlap" in lib.rbsm_last_error().decode()
+
+
+def test_tune_cache_file_round_trip(lib, tmp_path):
+    """The autotuner cache is host state: loading, saving and clearing it
+    touch no GPU."""
+    import paper_1711_07793_amd as rb
+    rb.tune_cache_clear()
+    src = tmp_path / "tune.txt"
+    src.write_text("# comment\n"
+                   "gfx950-cu256/00000000deadbeef 64 1 2048 1 2 4 -1\n"
+                   "gfx950-cu256/0123456789abcdef 32 2 3072 0 2 4 5\n")
+    assert rb.tune_cache_load(str(src)) == 2
+    out = tmp_path / "saved.txt"
+    rb.tune_cache_save(str(out))
+    lines = sorted(l for l in out.read_text().splitlines() if not l.startswith("#"))
+    assert lines == ["gfx950-cu256/00000000deadbeef 64 1 2048 1 2 4 -1",
+                     "gfx950-cu256/0123456789abcdef 32 2 3072 0 2 4 5"]
+    rb.tune_cache_clear()
+    rb.tune_cache_save(str(out))
+    assert [l for l in out.read_text().splitlines() if not l.startswith("#")] == []
+
+
+@pytest.mark.parametrize("line", ["key 24 1 2048 0 2 4 -1", "key 32 1 2048 0 3 4 -1", "key 32 1 2048 2 2 4 -1",
+                                  "key 32 1", "key 32 9 2048 0 2 4 -1", "key 32 1 2048 0 2 4 13",
+                                  "key 32 1 2048 0 2 4"])
+def test_tune_cache_rejects_bad_entries(lib, tmp_path, line):
+    import paper_1711_07793_amd as rb
+    f = tmp_path / "bad.txt"
+    f.write_text(line + "\n")
+    with pytest.raises(rb.RbsmError):
+        rb.tune_cache_load(str(f))
+    with pytest.raises(rb.RbsmError):
+        rb.tune_cache_load(str(tmp_path / "missing.txt"))
+    rb.tune_cache_clear()

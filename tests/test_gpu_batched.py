@@ -85,14 +85,20 @@ def test_autotune_and_tunings_never_change_results(rb, workload):
     plan.launch()
     torch.cuda.synchronize()
     want = [j["out"].cpu().numpy().copy() for j in jobs]
-    for t in (rb.RbsmTuning(16, 1, 256), rb.RbsmTuning(64, 3, 4096)):
+    tunings = [rb.RbsmTuning(16, 1, 256), rb.RbsmTuning(64, 3, 4096),
+               # tiles dealt to XCDs in chunks (with a partial last round)
+               rb.RbsmTuning(32, 1, 2048, xcd_chunk=0), rb.RbsmTuning(32, 1, 2048, xcd_chunk=3),
+               rb.RbsmTuning(16, 2, 2048, xcd_chunk=12),
+               # resident workgroups looping over tiles, every walk blocking
+               *[rb.RbsmTuning(tw, 1, 2048, 1, wf, wb) for tw in (16, 64) for wf in (1, 2, 4) for wb in (4, 8)]]
+    for t in tunings:
         plan.tuning = t
         for j in jobs:
             j["out"].fill_(3)
         plan.launch()
         torch.cuda.synchronize()
         for k, j in enumerate(jobs):
-            assert np.array_equal(j["out"].cpu().numpy(), want[k]), (k, t.tile_w)
+            assert np.array_equal(j["out"].cpu().numpy(), want[k]), (k, t.as_dict())
     chosen = plan.autotune(reps=2)
     assert chosen.tile_w in (16, 32, 64)
     for j in jobs:
