@@ -1,18 +1,20 @@
 """Benchmark of the RBSM per-fragment shadow pass on one MI355X.
 
-One step = one plain per-view pass of the hot path over one frame: hard RBSM
-(silhouette recovery) of 1920x1080 perspective-camera fragments against a
-2048^2 float32 depth map of 64 random triangles over a tilted receiver,
-MAXDIST 32, depth bias 1e-4 (the paper's 2048^2 / 1080p hard-shadow
-operating point, Table 3, on synthetic scenes).  Frames rotate over at least
-512 MB of distinct device buffers so their bytes come from HBM, not from the
-256 MB last-level cache.  All inputs are resident on the device before timing.
+One step = one frame of the batched workload through the whole hot path:
+16 shadow maps of uneven sizes (a directional light's cascades 8192^2 ..
+1024^2 and 12 spot maps 1024^2 .. 4096^2, random-triangle scenes) and 8 views
+(two each of 1280x720, 1920x1080, 2560x1440, 3840x2160) split into 48
+(view, light) jobs -- hard RBSM on the cascades, RSMSS radius 0 on the spot
+lights -- 66.55 M fragment evaluations, run as one replay of the captured
+batched plan.  The frame's inputs (1.6 GB) are resident in HBM before timing
+and exceed the 256 MB last-level cache, so every frame streams from HBM.
 
-Prints ONE JSON line.  Besides the headline value it reports the dominant
-kernel's roofline (algorithmic bytes / kernel time from HIP events recorded
-around every launch on the launch stream), the RSMSS pass at 3840x2160 on a
-4096^2 map with the thin-bar fence, the plain shadow-mapping pass of the same
-frames, and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line: the headline (batched fragments/s), the plain
+per-view launches of the same jobs, p50/p99 frame latency, the dominant
+kernel's roofline (algorithmic bytes / kernel time from HIP events on its
+launch stream), extras (the single-view hard pass at 2048^2 / 1080p, RSMSS
+and RPCF at 4K, 512^2 uniform frames, the per-light-radius batched variant,
+serving, rasterization, compositing) and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -32,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "shaded fragments/sec (RBSM, RSMSS) batched vs plain per-view; p99 frame latency"
 PEAK_HBM_GBPS = 8000.0
 ROTATE_BYTES = 512 << 20
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "tile_kernel_hard_tri64_map2048_1080p_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "batch_kernel_16maps_8views_traffic.md")
 
 
 def kernel_source_hash() -> str:
@@ -45,22 +47,35 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_hash: str):
+def read_traffic(kernel_hash: str, tuning: dict, path: str = PROFILE_TRAFFIC):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+    None when it is missing or was taken on a different kernel source or
+    launch tuning."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PROFILE_TRAFFIC):
+    for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha") != kernel_hash:
+    if vals.get("kernel_source_sha") != kernel_hash or vals.get("tuning") != tuning_label(tuning):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def tuning_label(t: dict) -> str:
+    return ",".join(f"{k}={t[k]}" for k in ("tile_w", "apron", "lds_cap", "persistent", "walk_first", "walk_block",
+                                            "xcd_chunk"))
+
+
+def kernel_instance(t: dict) -> str:
+    """Name of the batched kernel a tuning launches."""
+    if t["persistent"]:
+        return f"batch_persistent_kernel<{t['tile_w']}, {t['walk_first']}, {t['walk_block']}>"
+    return f"batch_kernel<{t['tile_w']}>"
 
 
 class Frames:
@@ -103,16 +118,19 @@ def time_pass(torch, rb, lib, fn_name, frames: Frames, params, steps: int, warmu
         assert st == 0, rb.rbsm_last_error()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # the timed steps continue the rotation, so the first of them reads the
+    # slot touched longest ago, not one the warm-up left in the cache
+    first = warmup % nslot
     t0 = time.perf_counter()
     ev0.record(stream)
     for k in range(steps):
-        a = args[k % nslot]
+        a = args[(first + k) % nslot]
         fn(a[0], a[1], a[2], a[3], a[4], sh)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     avg_ms = ev0.elapsed_time(ev1) / steps
-    used = [k % nslot for k in range(steps)]
+    used = [(first + k) % nslot for k in range(steps)]
     return wall, avg_ms, used
 
 
@@ -164,86 +182,157 @@ def copy_bandwidth(torch, nbytes: int = 256 << 20, reps: int = 5) -> float:
     return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
 
 
-def batched_section(torch, rb, frames_timed: int = 20):
-    """The batched workload (16 maps, 8 views, 48 jobs of uneven size) run as
-    plain per-view launches (one call per job, frame-synchronised), as one
-    batched launch per frame, and as one graph replay per frame."""
-    import synth
-    w = synth.make_batched(4001)
-    maps = [torch.from_numpy(m).cuda() for m in w["maps"]]
-    jobs = []
-    for j in w["jobs"]:
-        f = torch.from_numpy(j["frags"]).cuda()
-        out = torch.empty(len(j["frags"]), dtype=torch.uint8 if j["mode"] == 0 else torch.float32, device="cuda")
-        jobs.append(dict(map=maps[j["map"]], frags=f, params=j["params"], mode=j["mode"], out=out))
-    n_frag = sum(j["frags"].numel() // 3 for j in jobs)
-    lib = rb.load_library()
+class BatchedFrame:
+    """The batched workload on the device: 16 maps, 8 views, 48 jobs (one
+    output buffer per job), plus the frame's algorithmic bytes."""
+
+    def __init__(self, torch, rb, seed: int = 4001, radius_per_light: bool = False):
+        import synth
+        w = synth.make_batched(seed)
+        self.maps = [torch.from_numpy(m).cuda() for m in w["maps"]]
+        self.jobs = []
+        radii = {}
+        for j in w["jobs"]:
+            params = dict(j["params"])
+            if radius_per_light and j["mode"] == 1:
+                # each spot light's own kernel radius 3..15 (one per light)
+                radii.setdefault(j["map"], 3 + int(synth.uniform_floats(seed * 7 + j["map"], 1)[0] * 13))
+                params["kernel_radius"] = radii[j["map"]]
+            f = torch.from_numpy(j["frags"]).cuda()
+            out = torch.empty(len(j["frags"]), dtype=torch.uint8 if j["mode"] == 0 else torch.float32, device="cuda")
+            self.jobs.append(dict(map=self.maps[j["map"]], frags=f, params=params, mode=j["mode"], out=out))
+        self.radii = radii
+        self.n_frag = sum(j["frags"].numel() // 3 for j in self.jobs)
+        self.resident_bytes = sum(t.numel() * t.element_size() for t in self.maps) + sum(
+            j["frags"].numel() * 4 + j["out"].numel() * j["out"].element_size() for j in self.jobs)
+        lib = rb.load_library()
+        self.cparams = [rb.Params(**j["params"]).to_c() for j in self.jobs]
+        self.lib = lib
+
+    def frame_bytes(self, rb) -> int:
+        """12 B per fragment in, 1 (hard) or 4 (RSMSS) B out, and 4 B per
+        distinct texel each job reads (counted on the device)."""
+        total = 0
+        for j in self.jobs:
+            n = j["frags"].numel() // 3
+            t = rb.rbsm_footprint(j["map"], j["frags"], j["params"], j["mode"])
+            total += (12 + (1 if j["mode"] == 0 else 4)) * n + 4 * int(t.sum().item())
+            del t
+        return total
+
+    def plain_frame(self, stream_handle: int):
+        """One call per job (the plain entry points), in job order."""
+        for j, p in zip(self.jobs, self.cparams):
+            fn = self.lib.rbsm_visibility if j["mode"] == 0 else self.lib.rsmss_visibility
+            st = fn(j["map"].data_ptr(), j["frags"].data_ptr(), j["frags"].numel() // 3, ctypes.byref(p),
+                    j["out"].data_ptr(), stream_handle)
+            assert st == 0, self.lib.rbsm_last_error()
+
+    def outputs(self):
+        return [j["out"].clone() for j in self.jobs]
+
+    def equal(self, want) -> bool:
+        import torch
+        return all(torch.equal(j["out"], w) for j, w in zip(self.jobs, want))
+
+
+def frame_rate(torch, frame_fn, sync_fn, n_frag: int, frames: int, warmup: int = 3):
+    """Frames run one at a time, each synchronised (a renderer waiting for
+    its shadow buffers): fragments/s and p50/p99 frame latency (host clock)."""
+    for _ in range(warmup):
+        frame_fn()
+    sync_fn()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        a = time.perf_counter()
+        frame_fn()
+        sync_fn()
+        lat.append((time.perf_counter() - a) * 1e3)
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"fragments_per_s": n_frag * frames / wall, "p50_frame_ms": float(np.percentile(lat, 50)),
+            "p99_frame_ms": float(np.percentile(lat, 99)), "frames": frames}
+
+
+def batched_headline(torch, rb, bf: BatchedFrame, steps: int, warmup: int, latency_frames: int = 200):
+    """The headline: plain per-view launches of the 48 jobs, then the
+    autotuned batched plan captured as a HIP graph.  Exactly `steps` graph
+    replays run back to back between synchronisations; one HIP event pair on
+    the replay stream brackets them (the kernel's average duration)."""
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
-    cparams = [rb.Params(**j["params"]).to_c() for j in jobs]
-
-    def plain_frame():
-        for j, p in zip(jobs, cparams):
-            fn = lib.rbsm_visibility if j["mode"] == 0 else lib.rsmss_visibility
-            st = fn(j["map"].data_ptr(), j["frags"].data_ptr(), j["frags"].numel() // 3, ctypes.byref(p),
-                    j["out"].data_ptr(), sh)
-            assert st == 0, rb.rbsm_last_error()
-
-    def run(frame_fn, sync_fn):
-        for _ in range(3):
-            frame_fn()
-        sync_fn()
-        lat = []
-        t0 = time.perf_counter()
-        for _ in range(frames_timed):
-            a = time.perf_counter()
-            frame_fn()
-            sync_fn()
-            lat.append((time.perf_counter() - a) * 1e3)
-        wall = time.perf_counter() - t0
-        lat = np.array(lat)
-        return {"fragments_per_s": n_frag * frames_timed / wall, "p50_frame_ms": float(np.percentile(lat, 50)),
-                "p99_frame_ms": float(np.percentile(lat, 99))}
-
-    plain = run(plain_frame, torch.cuda.synchronize)
-    want = [j["out"].clone() for j in jobs]
-    plan = rb.Plan(jobs)
-    tune = plan.autotune(reps=3)
-    for j in jobs:
+    plain = frame_rate(torch, lambda: bf.plain_frame(sh), torch.cuda.synchronize, bf.n_frag, 30)
+    want = bf.outputs()
+    plan = rb.Plan(bf.jobs)
+    tune = plan.autotune(reps=3).as_dict()
+    for j in bf.jobs:
         j["out"].fill_(0)
     plan.launch()
     torch.cuda.synchronize()
-    equal = all(torch.equal(j["out"], wv) for j, wv in zip(jobs, want))
-    batched = run(plan.launch, torch.cuda.synchronize)
+    equal = bf.equal(want)
+    eager = frame_rate(torch, plan.launch, torch.cuda.synchronize, bf.n_frag, 30)
     s = torch.cuda.Stream()
     s.wait_stream(stream)
     plan.capture(s)
-    graph = run(lambda: plan.launch(s), s.synchronize)
+    for _ in range(warmup):
+        plan.launch(s)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(s)
+    for _ in range(steps):
+        plan.launch(s)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_ms = ev0.elapsed_time(ev1) / steps
+    graph_equal = bf.equal(want)
+    # per-frame latency: single replays, each bracketed by events and waited for
+    lat = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(latency_frames):
+        e0.record(s)
+        plan.launch(s)
+        e1.record(s)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
     plan.close()
-    # algorithmic bytes of one frame: 12 B per fragment in, the outputs, and
-    # 4 B per distinct texel each job reads (counted on the device)
-    frame_bytes = 0
-    for j in jobs:
-        n = j["frags"].numel() // 3
-        t = rb.rbsm_footprint(j["map"], j["frags"], j["params"], j["mode"])
-        frame_bytes += (12 + (1 if j["mode"] == 0 else 4)) * n + 4 * int(t.sum().item())
-        del t
-    for res in (plain, batched, graph):
-        res["achieved_GBps"] = frame_bytes * res["fragments_per_s"] / n_frag / 1e9
     return {
-        "workload": "16 maps (cascades 8192^2..1024^2 + 12 spot maps 1024^2..4096^2), 8 views 720p..4K, "
-                    f"{len(jobs)} jobs (cascades hard, spots RSMSS r=0)",
-        "fragments_per_frame": n_frag,
-        "algorithmic_bytes_per_frame": frame_bytes,
-        "hbm_peak_GBps": 8000.0,
-        "plain_per_view": plain,
-        "batched": batched,
-        "batched_graph": graph,
-        "speedup_vs_plain": batched["fragments_per_s"] / plain["fragments_per_s"],
-        "graph_speedup_vs_plain": graph["fragments_per_s"] / plain["fragments_per_s"],
-        "tuning": {"tile_w": tune.tile_w, "apron": tune.apron, "lds_cap": tune.lds_cap},
-        "bitwise_equal_to_plain": bool(equal),
+        "wall_s": wall, "avg_kernel_ms": avg_ms, "tuning": tune,
+        "p50_frame_ms": float(np.percentile(lat, 50)), "p99_frame_ms": float(np.percentile(lat, 99)),
+        "plain_per_view": plain, "batched_eager": eager,
+        "bitwise_equal_to_plain": bool(equal and graph_equal),
     }
+
+
+def batched_radius_section(torch, rb, frames: int = 10):
+    """The per-light-radius variant of the batched workload: every spot light
+    filters with its own RPCF radius 3..15 (RSMSS box-averaged), cascades stay
+    hard.  Plain per-view launches vs the plan (one graph replay per frame)."""
+    bf = BatchedFrame(torch, rb, radius_per_light=True)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    plain = frame_rate(torch, lambda: bf.plain_frame(sh), torch.cuda.synchronize, bf.n_frag, frames, warmup=1)
+    want = bf.outputs()
+    plan = rb.Plan(bf.jobs)
+    plan.autotune(reps=1)
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    plan.capture(s)
+    for j in bf.jobs:
+        j["out"].fill_(0)
+    graph = frame_rate(torch, lambda: plan.launch(s), s.synchronize, bf.n_frag, frames, warmup=1)
+    equal = bf.equal(want)
+    plan.close()
+    terms = sum((j["frags"].numel() // 3) * (2 * j["params"]["kernel_radius"] + 1) ** 2 for j in bf.jobs)
+    return {"workload": "batched workload with each spot light's own RPCF radius "
+                        f"({sorted(set(bf.radii.values()))}), cascades hard",
+            "fragments_per_frame": bf.n_frag, "rsmss_terms_per_frame": terms,
+            "plain_per_view": plain, "batched_graph": graph,
+            "speedup_vs_plain": graph["fragments_per_s"] / plain["fragments_per_s"],
+            "bitwise_equal_to_plain": bool(equal)}
 
 
 def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: int = 4 << 30,
@@ -457,55 +546,175 @@ def composite_section(torch, rb, reps: int = 50):
             "bytes_per_launch": nbytes, "achieved_GBps": nbytes / (ms * 1e-3) / 1e9, "hbm_peak_GBps": 8000.0}
 
 
-def cpu_baseline(frames: Frames, budget_s: float):
-    """The oracle (single-threaded C, unchanged) on a bounded sample of the
-    same frames: first on one core, then fanned out over the host's cores by
-    static fragment slices (one thread per slice; the C calls release the
-    interpreter lock).  Reported value: the all-cores rate."""
+def host_threads() -> tuple:
+    """Threads for the CPU leg: the CPUs this process may run on (its
+    affinity), capped by OMP_NUM_THREADS where the host sets one (a GPU machine
+    gives each GPU a share of its cores that way).  Returns (threads,
+    affinity size, os.cpu_count())."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(aff, cap) if cap > 0 else aff
+    return max(1, threads), aff, os.cpu_count()
+
+
+def cpu_baseline(budget_s: float, subset: int = 1 << 20, seed: int = 4001):
+    """The oracle (single-threaded C, unchanged) on a fixed 2^20-fragment
+    subset of the batched workload: every job contributes the same share of
+    its rows, so the subset keeps the frame's mix of maps, modes and views.
+    Passes over the subset repeat for budget_s / 2 on one thread, then for
+    budget_s / 2 fanned out over the host's threads by static fragment
+    slices (the C calls release the interpreter lock).  Reported value: the
+    all-threads rate."""
     import threading
     import oracle
+    import synth
+    w = synth.make_batched(seed)
+    total = sum(len(j["frags"]) for j in w["jobs"])
+    parts = []
+    for j in w["jobs"]:
+        k = max(1, round(len(j["frags"]) * subset / total))
+        parts.append((w["maps"][j["map"]], np.ascontiguousarray(j["frags"][:k]), j["params"], j["mode"]))
+    n_sub = sum(len(p[1]) for p in parts)
+
+    def run_slice(a, b):
+        """Fragments [a, b) of the subset (in job order)."""
+        done, base = 0, 0
+        for m, f, prm, mode in parts:
+            lo, hi = max(a - base, 0), min(b - base, len(f))
+            if lo < hi:
+                (oracle.rbsm_hard if mode == 0 else oracle.rsmss)(m, f[lo:hi], prm)
+                done += hi - lo
+            base += len(f)
+        return done
 
     def run_for(seconds, threads):
         done = [0] * threads
         stop = time.perf_counter() + seconds
-        frames_done = [0]
 
-        def worker(w):
-            k = 0
-            while time.perf_counter() < stop:
-                h = frames.host[k % len(frames.host)]
-                n = len(h["frags"])
-                lo, hi = n * w // threads, n * (w + 1) // threads
-                oracle.rbsm_hard(h["map"], h["frags"][lo:hi], h["params"])
-                done[w] += hi - lo
-                k += 1
-            if w == 0:
-                frames_done[0] = k
+        def worker(t):
+            a, b = n_sub * t // threads, n_sub * (t + 1) // threads
+            while True:
+                done[t] += run_slice(a, b)
+                if time.perf_counter() >= stop:
+                    break
 
         t0 = time.perf_counter()
-        ts = [threading.Thread(target=worker, args=(w,)) for w in range(threads)]
+        ts = [threading.Thread(target=worker, args=(t,)) for t in range(threads)]
         for th in ts:
             th.start()
         for th in ts:
             th.join()
         dt = time.perf_counter() - t0
-        return sum(done) / dt, sum(done), dt, frames_done[0]
+        return sum(done) / dt, sum(done), dt
 
-    single, n1, dt1, k1 = run_for(budget_s / 2, 1)
-    cores = max(1, min(16, os.cpu_count() or 1))
-    multi, nm, dtm, km = run_for(budget_s / 2, cores)
-    return dict(value=multi, unit="fragments/s", cores=cores, kind="oracle",
-                single_thread_value=single,
-                sample=f"whole frames of the same workload, 5 scenes cycled: {n1} fragments in {dt1:.1f} s on "
-                       f"one thread, then {nm} fragments in {dtm:.1f} s on {cores} threads (each thread a "
-                       f"static slice of every frame)")
+    single, n1, dt1 = run_for(budget_s / 2, 1)
+    threads, aff, ncpu = host_threads()
+    multi, nm, dtm = run_for(budget_s / 2, threads)
+    return dict(value=multi, unit="fragments/s", cores=threads, kind="oracle",
+                single_thread_value=single, host_cpu_count=ncpu, affinity_cpus=aff,
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"),
+                sample=f"fixed {n_sub}-fragment subset of the batched workload (every job's first rows, in "
+                       f"proportion): {n1} fragments in {dt1:.1f} s on one thread, then {nm} fragments in "
+                       f"{dtm:.1f} s on {threads} threads (static slices)")
+
+
+def uniform_section(torch, rb, steps: int = 2000, n_frames: int = 280):
+    """The 512^2 single-quad workload: 65,536 uniformly scattered fragments per
+    frame (no screen locality), hard RBSM, MAXDIST 16.  n_frames distinct
+    frames (>= 512 MB) rotate through the timed launches."""
+    import synth
+    lib = rb.load_library()
+    slots = []
+    for k in range(n_frames):
+        c = synth.make_config(1, 1000 + 1 + k)
+        m = torch.from_numpy(c["map"]).cuda()
+        f = torch.from_numpy(c["frags"]).cuda()
+        o = torch.empty(len(c["frags"]), dtype=torch.uint8, device="cuda")
+        slots.append((m, f, o, rb.Params(**c["params"]).to_c()))
+    n = len(c["frags"])
+    resident = n_frames * (512 * 512 * 4 + n * 13)
+    stream = torch.cuda.current_stream()
+    sh = int(stream.cuda_stream)
+    for k in range(20):
+        m, f, o, p = slots[k % n_frames]
+        assert lib.rbsm_visibility(m.data_ptr(), f.data_ptr(), n, ctypes.byref(p), o.data_ptr(), sh) == 0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(steps):
+        m, f, o, p = slots[(20 + k) % n_frames]
+        lib.rbsm_visibility(m.data_ptr(), f.data_ptr(), n, ctypes.byref(p), o.data_ptr(), sh)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_ms = ev0.elapsed_time(ev1) / steps
+    # algorithmic bytes of a few frames: fragments in, mask out, distinct texels
+    per = []
+    for m, f, o, p in slots[:8]:
+        params = dict(width=512, height=512, pitch=512, depth_bias=1e-4, max_dist=16)
+        t = rb.rbsm_footprint(m, f, params, 0)
+        per.append(13 * n + 4 * int(t.sum().item()))
+    b = float(np.mean(per))
+    return {"workload": "hard RBSM, 512x512 map of one rotated quad, 65,536 uniform fragments per frame, MAXDIST 16",
+            "frames_rotated": n_frames, "resident_bytes": resident, "fragments_per_s": n * steps / wall,
+            "avg_kernel_ms": avg_ms, "algorithmic_bytes_per_launch": b,
+            "achieved_GBps": b / (avg_ms * 1e-3) / 1e9}
+
+
+def single_view_section(torch, rb, steps: int):
+    """The single-view hard pass: 2048^2 map of 64 triangles, 1920x1080
+    perspective fragments, MAXDIST 32; 13 distinct frames rotate."""
+    lib = rb.load_library()
+    frames = Frames(torch, 2, [2001, 2002, 2003, 2004, 2005], ROTATE_BYTES, "hard", torch.uint8)
+    params = frames.params
+    wall, avg_ms, used = time_pass(torch, rb, lib, "rbsm_visibility", frames, params, steps, 20)
+    per_frame = algorithmic_bytes(torch, rb, frames, params, 0, 1)
+    scene = [s[0] for s in frames.slots]
+    bpl = float(np.mean([per_frame[scene[u]] for u in used]))
+    p50, p99 = launch_latency(torch, rb, lib, "rbsm_visibility", frames, params, 300)
+    w_sm, a_sm, _ = time_pass(torch, rb, lib, "sm_visibility", frames, params, max(200, steps // 4), 20)
+    return {"workload": "hard RBSM, 2048x2048 map of 64 random triangles over a tilted receiver, 1920x1080 "
+                        "perspective fragments, MAXDIST 32, one plain launch per frame",
+            "fragments_per_s": frames.n * steps / wall, "ms_per_step": wall * 1e3 / steps,
+            "avg_kernel_ms": avg_ms, "algorithmic_bytes_per_launch": bpl,
+            "achieved_GBps": bpl / (avg_ms * 1e-3) / 1e9, "p50_frame_ms": p50, "p99_frame_ms": p99,
+            "frames_rotated": len(frames.slots),
+            "plain_sm": {"fragments_per_s": frames.n * max(200, steps // 4) / w_sm, "avg_kernel_ms": a_sm}}
+
+
+def rsmss_section(torch, rb, steps: int):
+    """RSMSS radius 0 and RPCF at the light's radius on the 4K fenced scene."""
+    lib = rb.load_library()
+    fr3 = Frames(torch, 3, [3001, 3002, 3003], ROTATE_BYTES, "rsmss", torch.float32)
+    p3 = dict(fr3.params, kernel_radius=0)
+    w3, a3, used3 = time_pass(torch, rb, lib, "rsmss_visibility", fr3, p3, steps, 10)
+    b3 = algorithmic_bytes(torch, rb, fr3, p3, 1, 4)
+    sc3 = [s[0] for s in fr3.slots]
+    bpl3 = float(np.mean([b3[sc3[u]] for u in used3]))
+    out = {"rsmss": {
+        "workload": "RSMSS r=0, 4096x4096 map of 256 triangles + thin-bar fence, 3840x2160 fragments, MAXDIST 16",
+        "fragments_per_s": fr3.n * steps / w3, "ms_per_step": w3 * 1e3 / steps, "avg_kernel_ms": a3,
+        "achieved_GBps": bpl3 / (a3 * 1e-3) / 1e9, "algorithmic_bytes_per_launch": bpl3}}
+    r3 = fr3.host[0]["light_radius"]
+    pr = dict(fr3.params, kernel_radius=r3)
+    steps_r = max(10, steps // 20)
+    wr, ar, _ = time_pass(torch, rb, lib, "rsmss_visibility", fr3, pr, steps_r, 3)
+    out["rpcf"] = {
+        "workload": f"RPCF radius {r3} ({(2 * r3 + 1) ** 2} RSMSS terms per fragment) on the RSMSS frames",
+        "kernel_radius": r3, "fragments_per_s": fr3.n * steps_r / wr, "ms_per_step": wr * 1e3 / steps_r,
+        "avg_kernel_ms": ar, "terms_per_s": fr3.n * (2 * r3 + 1) ** 2 / (ar * 1e-3)}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -520,24 +729,17 @@ def main():
     import torch
     import paper_1711_07793_amd as rb
 
-    lib = rb.load_library()
+    rb.load_library()
     torch.cuda.init()
 
-    # ---- headline: hard RBSM, 2048^2 map, 1920x1080 fragments -----------
-    frames = Frames(torch, 2, [2001, 2002, 2003, 2004, 2005], ROTATE_BYTES, "hard", torch.uint8)
-    params = frames.params
-    wall, avg_kernel_ms, used = time_pass(torch, rb, lib, "rbsm_visibility", frames, params, args.steps,
-                                          args.warmup)
-    ms_per_step = wall * 1e3 / args.steps
-    value = frames.n * args.steps / wall
-    per_frame_bytes = algorithmic_bytes(torch, rb, frames, params, 0, 1)
-    slot_scene = [s[0] for s in frames.slots]
-    bytes_per_launch = float(np.mean([per_frame_bytes[slot_scene[u]] for u in used]))
-    p50_ms, p99_ms = launch_latency(torch, rb, lib, "rbsm_visibility", frames, params, 500)
-    achieved = bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9
+    # ---- headline: the batched workload, one graph replay per step --------
+    bf = BatchedFrame(torch, rb)
+    h = batched_headline(torch, rb, bf, args.steps, args.warmup)
+    frame_bytes = bf.frame_bytes(rb)
+    value = bf.n_frag * args.steps / h["wall_s"]
+    achieved = frame_bytes / (h["avg_kernel_ms"] * 1e-3) / 1e9
     khash = kernel_source_hash()
-    traffic = read_traffic(khash)
-
+    tune = h["tuning"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -545,88 +747,64 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": h["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "hard RBSM, 2048x2048 f32 map of 64 random triangles over a tilted receiver, "
-                        "1920x1080 perspective fragments, MAXDIST 32, bias 1e-4, plain per-view launch",
-            "fragments_per_step": frames.n,
-            "frames_rotated": len(frames.slots),
-            "resident_bytes": frames.bytes_resident,
+            "workload": "batched: 16 maps (cascades 8192^2, 4096^2, 2048^2, 1024^2 + 12 spot maps 1024^2..4096^2, "
+                        "64-triangle scenes), 8 views (2x 720p, 1080p, 1440p, 4K), 48 jobs (cascades hard RBSM, "
+                        "spots RSMSS r=0), one captured-graph replay of the autotuned plan per step",
+            "fragments_per_step": bf.n_frag,
+            "jobs": len(bf.jobs),
+            "resident_bytes": bf.resident_bytes,
+            "tuning": tune,
         },
+        "plain_per_view": h["plain_per_view"],
+        "batched_eager": h["batched_eager"],
+        "speedup_vs_plain": value / h["plain_per_view"]["fragments_per_s"],
+        "p50_frame_ms": h["p50_frame_ms"],
+        "p99_frame_ms": h["p99_frame_ms"],
+        "bitwise_equal_to_plain": h["bitwise_equal_to_plain"],
         "roofline": {
-            "kernel": "tile_kernel<true, 32> (hard pass)",
+            "kernel": kernel_instance(tune) + " (batched plan, graph replay)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBPS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "avg_kernel_ms": avg_kernel_ms,
+            "traffic": read_traffic(khash, tune),
+            "algorithmic_bytes_per_launch": frame_bytes,
+            "avg_kernel_ms": h["avg_kernel_ms"],
             "kernel_source_sha": khash,
         },
-        "p50_frame_ms": p50_ms,
-        "p99_frame_ms": p99_ms,
     }
+    del bf
+    torch.cuda.empty_cache()
 
     if args.copy_calibration or not args.no_extras:
         out["copy_kernel_GBps"] = copy_bandwidth(torch)
 
     if not args.no_extras:
-        # plain shadow mapping of the same frames (the paper's baseline pass)
-        w_sm, a_sm, _ = time_pass(torch, rb, lib, "sm_visibility", frames, params, max(200, args.steps // 4), 20)
-        out["plain_sm"] = {"fragments_per_s": frames.n * max(200, args.steps // 4) / w_sm,
-                           "avg_kernel_ms": a_sm}
-        del frames
+        out["single_view_hard"] = single_view_section(torch, rb, max(200, args.steps))
         torch.cuda.empty_cache()
-        # RSMSS at 3840x2160 on a 4096^2 fenced scene, radius 0 (Listing 5 exactly)
-        fr3 = Frames(torch, 3, [3001, 3002, 3003], ROTATE_BYTES, "rsmss", torch.float32)
-        p3 = dict(fr3.params, kernel_radius=0)
-        steps3 = max(100, args.steps // 10)
-        w3, a3, used3 = time_pass(torch, rb, lib, "rsmss_visibility", fr3, p3, steps3, 10)
-        b3 = algorithmic_bytes(torch, rb, fr3, p3, 1, 4)
-        sc3 = [s[0] for s in fr3.slots]
-        bpl3 = float(np.mean([b3[sc3[u]] for u in used3]))
-        out["rsmss"] = {
-            "workload": "RSMSS r=0, 4096x4096 map of 256 triangles + thin-bar fence, 3840x2160 fragments, "
-                        "MAXDIST 16",
-            "fragments_per_s": fr3.n * steps3 / w3,
-            "ms_per_step": w3 * 1e3 / steps3,
-            "avg_kernel_ms": a3,
-            "achieved_GBps": bpl3 / (a3 * 1e-3) / 1e9,
-            "algorithmic_bytes_per_launch": bpl3,
-        }
-        # RPCF at the light's own kernel radius (the same frames)
-        r3 = fr3.host[0]["light_radius"]
-        pr = dict(fr3.params, kernel_radius=r3)
-        steps_r = max(20, args.steps // 100)
-        wr, ar, _ = time_pass(torch, rb, lib, "rsmss_visibility", fr3, pr, steps_r, 3)
-        out["rpcf"] = {
-            "workload": f"RPCF radius {r3} ({(2 * r3 + 1) ** 2} RSMSS terms per fragment) on the RSMSS frames",
-            "kernel_radius": r3,
-            "fragments_per_s": fr3.n * steps_r / wr,
-            "ms_per_step": wr * 1e3 / steps_r,
-            "avg_kernel_ms": ar,
-            "terms_per_s": fr3.n * (2 * r3 + 1) ** 2 / (ar * 1e-3),
-        }
-        del fr3
+        out.update(rsmss_section(torch, rb, max(100, args.steps // 2)))
         torch.cuda.empty_cache()
-        out["batched"] = batched_section(torch, rb)
+        out["uniform_512"] = uniform_section(torch, rb, max(500, args.steps * 5))
+        torch.cuda.empty_cache()
+        try:
+            out["batched_per_light_radius"] = batched_radius_section(torch, rb)
+        except rb.RbsmError as e:
+            out["batched_per_light_radius"] = {"error": str(e)}
         torch.cuda.empty_cache()
         out["serving"] = serving_section(torch, rb)
         torch.cuda.empty_cache()
         out["raster"] = raster_section(torch, rb)
         out["composite"] = composite_section(torch, rb)
         torch.cuda.empty_cache()
-        frames = Frames.__new__(Frames)  # host frames for the CPU leg
-        import synth
-        frames.host = [synth.make_config(2, s) for s in (2001, 2002, 2003, 2004, 2005)]
-        out["cpu_baseline"] = cpu_baseline(frames, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
