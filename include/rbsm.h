@@ -162,17 +162,20 @@ int rbsm_pass_tuned(int32_t mode, const float *shadow_map, const float *frags, i
 
 /*
  * Batched form: many (view, light) passes of uneven sizes in one launch.
- * Every job is a hard (mode 0) or RSMSS radius-0 (mode 1) pass over its own
- * map, fragments and output; a plan launches one workgroup per screen tile of
- * every job, so small jobs share the GPU with large ones and a frame costs a
- * single launch (or a single graph replay).  Each output is bitwise the
- * result of the corresponding plain entry point.
+ * Every job is a hard (mode 0) or RSMSS (mode 1) pass over its own map,
+ * fragments and output.  The hard and RSMSS radius-0 jobs share one launch of
+ * the tile pass over every screen tile of every job (one workgroup per tile,
+ * or resident workgroups looping over them), so small jobs share the GPU with
+ * large ones; RSMSS jobs with kernel_radius > 0 (RPCF, Sec. 5.3) run the
+ * box-filter kernel, one launch each, before it.  A frame is one call (or one
+ * graph replay).  Each output is bitwise the result of the corresponding
+ * plain entry point.
  */
 typedef struct {
     const float *shadow_map;  /* device, as rbsm_visibility */
     const float *frags;       /* device, [3*n] */
     int64_t n;                /* fragments, >= 0 */
-    rbsm_params params;       /* kernel_radius must be 0 */
+    rbsm_params params;       /* kernel_radius 0, or > 0 for an RPCF job (mode 1) */
     int32_t mode;             /* 0: hard, out is uint8_t[n]; 1: RSMSS, out is float[n] */
     void *out;                /* device; must not overlap any input or other output */
 } rbsm_job;
@@ -185,8 +188,8 @@ typedef struct rbsm_plan rbsm_plan;  /* opaque; owns device tables */
 int rbsm_plan_create(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tune, rbsm_plan **plan);
 
 /* Replace the jobs (pointers, depth, bias...) keeping each job's fragment
- * count and view_width, so the tile layout is unchanged (synchronous copy;
- * call when no launch of the plan is in flight). */
+ * count, view_width and kernel_radius, so the tile layout is unchanged
+ * (synchronous copy; call when no launch of the plan is in flight). */
 int rbsm_plan_update(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs);
 
 /* Enqueue one batched pass on stream (graph replay after rbsm_plan_capture). */

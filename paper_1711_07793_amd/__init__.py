@@ -297,7 +297,7 @@ class Plan:
 
     ``jobs`` is a list of dicts with ``map`` (float32 device tensor [H, pitch]),
     ``frags`` (float32 device tensor [N, 3]), ``params`` (dict or Params,
-    kernel_radius 0), ``mode`` (0 hard, 1 RSMSS) and ``out`` (uint8 [N] or
+    kernel_radius 0, or > 0 for an RPCF job in mode 1), ``mode`` (0 hard, 1 RSMSS) and ``out`` (uint8 [N] or
     float32 [N] device tensor).  The tensors are kept alive by the plan.
     """
 

@@ -175,6 +175,7 @@ struct rbsm_plan {
     uint16_t *d_block_job = nullptr;
     int64_t blocks = 0;
     int64_t grid = 0;  // workgroups of a persistent launch (resident ones, at most blocks)
+    std::vector<int32_t> rpcf_jobs;  // jobs with kernel_radius > 0, launched after the tile pass
     int64_t fragments = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -200,24 +201,43 @@ int64_t plan_grid(const rbsm_plan *p);
 
 // Validate jobs and build (and upload) the device job table and the
 // block -> job map for the plan's tile width.
-int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool keep_layout) {
-    const char *fn = keep_layout ? "rbsm_plan_update" : "rbsm_plan_create";
-    if (!jobs || n_jobs < 1 || n_jobs > 65535) return fail(RBSM_ERR_INVALID_ARG, "%s: need 1..65535 jobs", fn);
-    if (keep_layout && (size_t)n_jobs != plan->jobs.size())
-        return fail(RBSM_ERR_INVALID_ARG, "%s: job count differs from the plan", fn);
-    std::vector<JobDev> dev(n_jobs);
+// Host-side tables of a batch: the device job records, the block -> job map
+// of the tile pass (when wanted) and the RPCF jobs, after validating every
+// job and every overlap.
+struct HostTables {
+    std::vector<JobDev> dev;
     std::vector<uint16_t> block_job;
+    std::vector<int32_t> rpcf;
+    int64_t tiles = 0, frags = 0;
+};
+
+int make_tables(const char *fn, const rbsm_job *jobs, int32_t n_jobs, int tile_w, const std::vector<rbsm_job> *same_layout,
+                bool want_map, HostTables &T) {
+    if (!jobs || n_jobs < 1 || n_jobs > 65535) return fail(RBSM_ERR_INVALID_ARG, "%s: need 1..65535 jobs", fn);
+    if (same_layout && (size_t)n_jobs != same_layout->size())
+        return fail(RBSM_ERR_INVALID_ARG, "%s: job count differs from the plan", fn);
+    T.dev.assign(n_jobs, JobDev{});
+    T.block_job.clear();
+    T.rpcf.clear();
     int64_t base = 0, frags = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const rbsm_job &J = jobs[j];
         if (J.mode != 0 && J.mode != 1) return fail(RBSM_ERR_INVALID_ARG, "%s: job mode must be 0 or 1", fn);
         MapView mv;
-        const int st = validate(fn, J.shadow_map, J.frags, J.n, &J.params, J.out, J.mode == 0 ? 1 : 4, false, &mv);
+        const int st = validate(fn, J.shadow_map, J.frags, J.n, &J.params, J.out, J.mode == 0 ? 1 : 4, J.mode == 1,
+                                &mv);
         if (st != RBSM_OK) return st;
-        if (keep_layout && (J.n != plan->jobs[j].n || J.params.view_width != plan->jobs[j].params.view_width))
-            return fail(RBSM_ERR_INVALID_ARG, "%s: a job's n or view_width differs from the plan", fn);
-        const JobLayout L = job_layout(J.n, J.params.view_width, plan->tune.tile_w);
-        JobDev &D = dev[j];
+        if (same_layout && (J.n != (*same_layout)[j].n || J.params.view_width != (*same_layout)[j].params.view_width ||
+                            J.params.kernel_radius != (*same_layout)[j].params.kernel_radius))
+            return fail(RBSM_ERR_INVALID_ARG, "%s: a job's n, view_width or kernel_radius differs from the plan", fn);
+        // RPCF jobs (radius > 0) run their own kernel: no tiles in the tile pass
+        const bool rpcf = J.mode == 1 && J.params.kernel_radius > 0;
+        JobLayout L = job_layout(J.n, J.params.view_width, tile_w);
+        if (rpcf) {
+            L.tiles = 0;
+            T.rpcf.push_back(j);
+        }
+        JobDev &D = T.dev[j];
         D.m = mv;
         D.frags = J.frags;
         D.out = J.out;
@@ -230,7 +250,8 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
         D.mode = J.mode;
         D.vec_ok = ((uintptr_t)J.frags % 16 == 0) && ((uintptr_t)J.out % (J.mode == 0 ? 4 : 16) == 0) &&
                    (L.vw % 4 == 0);
-        for (int64_t b = 0; b < L.tiles; ++b) block_job.push_back((uint16_t)j);
+        if (want_map)
+            for (int64_t b = 0; b < L.tiles; ++b) T.block_job.push_back((uint16_t)j);
         base += L.tiles;
         frags += J.n;
     }
@@ -248,6 +269,17 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
         }
     }
     if (base > ((int64_t)1 << 24)) return fail(RBSM_ERR_INVALID_ARG, "%s: more than 2^24 tiles", fn);
+    T.tiles = base;
+    T.frags = frags;
+    return RBSM_OK;
+}
+
+int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool keep_layout) {
+    const char *fn = keep_layout ? "rbsm_plan_update" : "rbsm_plan_create";
+    HostTables T;
+    const int st = make_tables(fn, jobs, n_jobs, plan->tune.tile_w, keep_layout ? &plan->jobs : nullptr, true, T);
+    if (st != RBSM_OK) return st;
+    const int64_t base = T.tiles;
     if (!keep_layout || base != plan->blocks) {
         free_tables(plan);
         if (hipMalloc(&plan->d_jobs, sizeof(JobDev) * (size_t)n_jobs) != hipSuccess ||
@@ -256,13 +288,14 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
             return fail(RBSM_ERR_HIP, "%s: could not allocate the job tables", fn);
         }
     }
-    if (hipMemcpy(plan->d_jobs, dev.data(), sizeof(JobDev) * (size_t)n_jobs, hipMemcpyHostToDevice) != hipSuccess ||
-        (base > 0 && hipMemcpy(plan->d_block_job, block_job.data(), sizeof(uint16_t) * (size_t)base,
+    if (hipMemcpy(plan->d_jobs, T.dev.data(), sizeof(JobDev) * (size_t)n_jobs, hipMemcpyHostToDevice) != hipSuccess ||
+        (base > 0 && hipMemcpy(plan->d_block_job, T.block_job.data(), sizeof(uint16_t) * (size_t)base,
                                hipMemcpyHostToDevice) != hipSuccess))
         return fail(RBSM_ERR_HIP, "%s: could not upload the job tables", fn);
     plan->jobs.assign(jobs, jobs + n_jobs);
+    plan->rpcf_jobs = T.rpcf;
     plan->blocks = base;
-    plan->fragments = frags;
+    plan->fragments = T.frags;
     plan->grid = plan_grid(plan);
     return RBSM_OK;
 }
@@ -301,21 +334,36 @@ int64_t plan_grid(const rbsm_plan *p) {
     return std::min<int64_t>(p->blocks, resident_groups(batch_instance(p->tune), lds));
 }
 
-void launch_batch(const rbsm_plan *p, hipStream_t stream) {
-    if (p->blocks == 0) return;
-    const size_t lds = (size_t)p->tune.lds_cap * sizeof(float);
-    const void *k = batch_instance(p->tune);
-    const JobDev *jobs = p->d_jobs;
-    const uint16_t *bj = p->d_block_job;
-    int apron = p->tune.apron, cap = p->tune.lds_cap, chunk = p->tune.xcd_chunk;
-    int64_t tiles = p->blocks;
-    if (!p->tune.persistent) {
+// One batched pass: the RPCF jobs' box-filter kernels, then the tile pass
+// over every tile of the other jobs (tables in device memory).
+void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *bj, int64_t tiles, int64_t grid,
+                   const rbsm_job *host_jobs, const std::vector<int32_t> &rpcf, hipStream_t stream) {
+    for (const int32_t j : rpcf) {
+        const rbsm_job &J = host_jobs[j];
+        if (J.n == 0) continue;
+        MapView mv;
+        mv.t = J.shadow_map;
+        mv.pitch = J.params.pitch;
+        mv.W = J.params.width;
+        mv.H = J.params.height;
+        launch_rpcf(mv, J.frags, J.n, J.params.view_width, J.params.depth_bias, J.params.max_dist,
+                    J.params.kernel_radius, static_cast<float *>(J.out), stream);
+    }
+    if (tiles == 0) return;
+    const size_t lds = (size_t)tune.lds_cap * sizeof(float);
+    const void *k = batch_instance(tune);
+    int apron = tune.apron, cap = tune.lds_cap, chunk = tune.xcd_chunk;
+    if (!tune.persistent) {
         void *args[] = {(void *)&jobs, (void *)&bj, (void *)&apron, (void *)&cap, (void *)&chunk};
-        (void)hipLaunchKernel(k, dim3((unsigned)p->blocks), dim3(kT), args, lds, stream);
+        (void)hipLaunchKernel(k, dim3((unsigned)tiles), dim3(kT), args, lds, stream);
     } else {
         void *args[] = {(void *)&jobs, (void *)&bj, (void *)&tiles, (void *)&apron, (void *)&cap};
-        (void)hipLaunchKernel(k, dim3((unsigned)p->grid), dim3(kT), args, lds, stream);
+        (void)hipLaunchKernel(k, dim3((unsigned)grid), dim3(kT), args, lds, stream);
     }
+}
+
+void launch_batch(const rbsm_plan *p, hipStream_t stream) {
+    launch_tables(p->tune, p->d_jobs, p->d_block_job, p->blocks, p->grid, p->jobs.data(), p->rpcf_jobs, stream);
 }
 
 // Autotuner cache: the chosen tuning per (device, job mix).  The key names
@@ -347,6 +395,7 @@ std::string tune_key(const rbsm_plan *p) {
         mix(J.params.height);
         mix(J.params.pitch);
         mix(J.params.max_dist);
+        mix(J.params.kernel_radius);
         mix(J.mode);
     }
     char key[160];

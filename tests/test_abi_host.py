@@ -115,8 +115,9 @@ def test_plan_rejects_bad_jobs_on_host(lib):
     assert lib.rbsm_plan_create(jobs, 2, None, ctypes.byref(h)) == -1
     assert "overlap" in lib.rbsm_last_error().decode()
     q = _p(kernel_radius=2)
-    jobs[1] = rb.RbsmJob(0x1000000, 0x2000000, 64, q, 1, 0x3100000)  # radius > 0 not batched
+    jobs[1] = rb.RbsmJob(0x1000000, 0x2000000, 64, q, 0, 0x3100000)  # a radius on a hard job
     assert lib.rbsm_plan_create(jobs, 2, None, ctypes.byref(h)) == -1
+    assert "kernel_radius" in lib.rbsm_last_error().decode()
     assert lib.rbsm_plan_create(jobs, 0, None, ctypes.byref(h)) == -1
     assert lib.rbsm_plan_launch(None, None) == -1
     assert lib.rbsm_plan_fragments(None) == -1
@@ -202,3 +203,4 @@ def test_tune_cache_rejects_bad_entries(lib, tmp_path, line):
     with pytest.raises(rb.RbsmError):
         rb.tune_cache_load(str(tmp_path / "missing.txt"))
     rb.tune_cache_clear()
+

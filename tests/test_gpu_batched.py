@@ -206,3 +206,56 @@ def test_full_size_workload_sampled_against_oracle(rb):
     plan.close()
     del maps, jobs
     torch.cuda.empty_cache()
+
+
+def test_rpcf_jobs_in_the_plan(rb, workload):
+    """RSMSS jobs with a kernel radius (each spot light its own r) run the
+    box filter inside the plan: bitwise the plain rsmss_visibility result,
+    eager and from graph replays, and within 1e-5 of the oracle."""
+    maps, jobs = _device_jobs(rb, workload)
+    radii = {}
+    for k, j in enumerate(jobs):
+        if j["mode"] == 1:
+            r = radii.setdefault(id(j["map"]), 1 + (k % 6))
+            j["params"] = dict(j["params"], kernel_radius=r)
+    assert len(set(radii.values())) > 1
+    want = [_plain(rb, j) for j in jobs]
+    plan = rb.Plan(jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        assert np.array_equal(j["out"].cpu().numpy(), want[k]), k
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    plan.capture(s)
+    for rep in range(3):
+        for j in jobs:
+            j["out"].fill_(9)
+        torch.cuda.synchronize()
+        plan.launch(s)
+        s.synchronize()
+        for k, j in enumerate(jobs):
+            assert np.array_equal(j["out"].cpu().numpy(), want[k]), (rep, k)
+    rng = np.random.default_rng(11)
+    for k, j in enumerate(jobs):
+        if j["mode"] != 1:
+            continue
+        h = j["host"]
+        m = h.get("map_np")
+        if m is None:
+            m = workload["maps"][h["map"]]
+        n = len(h["frags"])
+        idx = np.sort(rng.choice(n, min(n, 400), replace=False))
+        f = np.ascontiguousarray(h["frags"][idx])
+        got = j["out"].cpu().numpy()[idx]
+        ref = oracle.rsmss(m, f, dict(j["params"], pitch=m.shape[1]))
+        assert np.max(np.abs(got.astype(np.float64) - ref)) <= 1e-5, k
+    # a radius change is a layout change: update rejects it
+    bad = [dict(j) for j in jobs]
+    for j in bad:
+        if j["mode"] == 1:
+            j["params"] = dict(j["params"], kernel_radius=j["params"]["kernel_radius"] + 1)
+            break
+    with pytest.raises(rb.RbsmError):
+        plan.update(bad)
+    plan.close()
