@@ -230,6 +230,24 @@ int64_t rbsm_plan_fragments(const rbsm_plan *plan);
 void rbsm_plan_destroy(rbsm_plan *plan);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one batched
+ * pass of `jobs`, as rbsm_plan_create + rbsm_plan_launch + rbsm_plan_destroy
+ * would run it (bitwise the same outputs), that allocates nothing.  The job
+ * table and the tile -> job map live in a 4 MiB array of the library's own
+ * in device memory, one per GPU, held until the process ends, and are
+ * rewritten by every call (job records travel in kernel arguments).
+ *   jobs, n_jobs   as rbsm_plan_create, at most 4096 jobs and 1,916,928
+ *                  screen tiles (about 1.9e9 fragments); larger requests
+ *                  return RBSM_ERR_INVALID_ARG before anything is enqueued
+ *   tune           NULL (defaults) or a valid tuning
+ *   stream         as the other entry points (asynchronous)
+ * Calls on one GPU share its array: a call's kernels must not overlap
+ * another call's on the same GPU (serialise them on one stream, or wait).
+ */
+int rbsm_batch_launch_noalloc(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tune, hipStream_t stream);
+
+/*
  * Shadow-map rasterization on the device: the light pass that produces the
  * depth map the pass consumes (Sec. 2 takes it as given), so a frame can stay
  * on the GPU from scene to visibility.

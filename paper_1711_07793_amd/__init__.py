@@ -136,6 +136,8 @@ def load_library() -> ctypes.CDLL:
     lib.rbsm_plan_fragments.restype = ctypes.c_int64
     lib.rbsm_plan_destroy.argtypes = [vp]
     lib.rbsm_plan_destroy.restype = None
+    lib.rbsm_batch_launch_noalloc.argtypes = [ctypes.POINTER(RbsmJob), ctypes.c_int32, ctypes.POINTER(RbsmTuning), vp]
+    lib.rbsm_batch_launch_noalloc.restype = ctypes.c_int
     d = ctypes.c_double
     lib.rbsm_rasterize.argtypes = [vp, ctypes.c_int32, d, d, d, ctypes.c_int32, ctypes.c_int32, i64, vp, vp]
     lib.rbsm_rasterize.restype = ctypes.c_int
@@ -374,6 +376,16 @@ class Plan:
             pass
 
 
+def batch_launch_noalloc(jobs, tuning=None, stream=None) -> None:
+    """One batched pass of ``jobs`` (as for ``Plan``) through the entry point
+    that allocates no device memory (its tables live in a per-GPU array of the
+    library).  Calls on one GPU must not overlap."""
+    arr, keep = Plan._marshal(jobs)
+    t = None if tuning is None else ctypes.byref(tuning if isinstance(tuning, RbsmTuning) else RbsmTuning(*tuning))
+    _call("rbsm_batch_launch_noalloc", arr, len(jobs), t, _stream(stream))
+    del keep
+
+
 PRIM_BYTES = 112  # sizeof(rbsm_prim)
 
 
@@ -525,5 +537,5 @@ class Engine:
             pass
 
 
-__all__ = ["tune_cache_load", "tune_cache_save", "tune_cache_clear", "Engine", "rbsm_rasterize", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
+__all__ = ["batch_launch_noalloc", "tune_cache_load", "tune_cache_save", "tune_cache_clear", "Engine", "rbsm_rasterize", "rbsm_composite", "RbsmRequest", "RbsmRequestLight", "RbsmEngineStats", "Plan", "RbsmJob", "Params", "RbsmParams", "RbsmTuning", "RbsmError", "rbsm_default_tuning", "rbsm_pass_tuned", "rbsm_visibility", "rsmss_visibility", "sm_visibility",
            "rbsm_footprint", "rbsm_last_error", "rbsm_abi_version", "load_library", "LIB_PATH"]

@@ -366,6 +366,72 @@ void launch_batch(const rbsm_plan *p, hipStream_t stream) {
     launch_tables(p->tune, p->d_jobs, p->d_block_job, p->blocks, p->grid, p->jobs.data(), p->rpcf_jobs, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Batched pass without allocation: its job table and block -> job map live in
+// one file-scope device array per GPU (shared by every call on that GPU).
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = (size_t)4 << 20;                      // 4 MiB per GPU
+constexpr int kScratchJobs = 4096;                                      // job records
+constexpr size_t kScratchJobBytes = (size_t)kScratchJobs * sizeof(JobDev);
+constexpr int64_t kScratchTiles = (int64_t)((kScratchBytes - kScratchJobBytes) / sizeof(uint16_t));
+static_assert(kScratchJobBytes % 256 == 0, "the block map starts 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy of the array at its own address; the
+// array's name in host code is not that address).
+int scratch_address(const char *fn, void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(RBSM_ERR_HIP, "%s: no current device (or an index beyond 63)", fn);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(RBSM_ERR_HIP, "%s: could not look up the scratch array's device address", fn);
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBSM_OK;
+}
+
+// Job records travel to the scratch table in kernel arguments (copied at
+// launch, so the caller's host memory may go at once, and capturable).
+constexpr int kChunkJobs = 32;
+struct JobChunk {
+    int32_t first, count;
+    JobDev jobs[kChunkJobs];
+};
+
+__global__ __launch_bounds__(64) void upload_jobs_kernel(const JobChunk c, JobDev *table) {
+    const int k = threadIdx.x;
+    if (k < c.count) table[c.first + k] = c.jobs[k];
+}
+
+// block_job[g] = the last job whose first tile is <= g (jobs without tiles
+// share their first tile with the next job, which the search prefers).
+__global__ __launch_bounds__(256) void block_job_kernel(const JobDev *__restrict__ jobs, int n_jobs, int64_t tiles,
+                                                        uint16_t *__restrict__ bj) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= tiles) return;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    bj[g] = (uint16_t)lo;
+}
+
 // Autotuner cache: the chosen tuning per (device, job mix).  The key names
 // the device (architecture and CU count) and hashes every job's layout
 // (fragment count, view width, map size and pitch, MAXDIST, mode) -- what
@@ -949,6 +1015,38 @@ void rbsm_engine_destroy(rbsm_engine *E) {
     if (E->s_copy) (void)hipStreamDestroy(E->s_copy);
     if (E->d_arena) (void)hipFree(E->d_arena);
     delete E;
+}
+
+int rbsm_batch_launch_noalloc(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tune, hipStream_t stream) {
+    const char *fn = "rbsm_batch_launch_noalloc";
+    if (tune && !tuning_ok(tune)) return fail(RBSM_ERR_INVALID_ARG, "%s: invalid tuning", fn);
+    rbsm_tuning t = tune ? *tune : rbsm_default_tuning();
+    if (!t.walk_first) t.walk_first = kWalkFirst;
+    if (!t.walk_block) t.walk_block = kWalkSteps;
+    if (n_jobs > kScratchJobs) return fail(RBSM_ERR_INVALID_ARG, "%s: at most 4096 jobs per call", fn);
+    HostTables T;
+    int st = make_tables(fn, jobs, n_jobs, t.tile_w, nullptr, false, T);
+    if (st != RBSM_OK) return st;
+    if (T.tiles > kScratchTiles)
+        return fail(RBSM_ERR_INVALID_ARG, "%s: the jobs need more than 1,916,928 screen tiles", fn);
+    void *base = nullptr;
+    if ((st = scratch_address(fn, &base)) != RBSM_OK) return st;
+    JobDev *d_jobs = static_cast<JobDev *>(base);
+    uint16_t *d_bj = reinterpret_cast<uint16_t *>(static_cast<char *>(base) + kScratchJobBytes);
+    for (int32_t first = 0; first < n_jobs; first += kChunkJobs) {
+        JobChunk c{};
+        c.first = first;
+        c.count = std::min(kChunkJobs, n_jobs - first);
+        for (int k = 0; k < c.count; ++k) c.jobs[k] = T.dev[first + k];
+        hipLaunchKernelGGL(upload_jobs_kernel, dim3(1), dim3(64), 0, stream, c, d_jobs);
+    }
+    if (T.tiles > 0)
+        hipLaunchKernelGGL(block_job_kernel, dim3((unsigned)((T.tiles + 255) / 256)), dim3(256), 0, stream,
+                           (const JobDev *)d_jobs, n_jobs, T.tiles, d_bj);
+    const size_t lds = (size_t)t.lds_cap * sizeof(float);
+    const int64_t grid = t.persistent ? std::min<int64_t>(T.tiles, resident_groups(batch_instance(t), lds)) : T.tiles;
+    launch_tables(t, d_jobs, d_bj, T.tiles, grid, jobs, T.rpcf, stream);
+    return launched(fn);
 }
 
 const char *rbsm_last_error(void) { return g_err; }

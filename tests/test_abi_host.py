@@ -204,3 +204,24 @@ def test_tune_cache_rejects_bad_entries(lib, tmp_path, line):
         rb.tune_cache_load(str(tmp_path / "missing.txt"))
     rb.tune_cache_clear()
 
+
+def test_noalloc_batch_rejects_oversized_requests_on_host(lib):
+    """The allocation-free entry point's limits (4096 jobs, 1,916,928 tiles)
+    and its argument checks come before any GPU call."""
+    import paper_1711_07793_amd as rb
+    p = _p(view_width=64)
+    jobs = (rb.RbsmJob * 4097)()
+    for k in range(4097):
+        jobs[k] = rb.RbsmJob(0x1000000, 0x2000000, 64, p, 0, 0x10000000 + 256 * k)
+    assert lib.rbsm_batch_launch_noalloc(jobs, 4097, None, None) == -1
+    assert "4096" in lib.rbsm_last_error().decode()
+    big = (rb.RbsmJob * 1)()
+    n = 1024 * 1916929  # one tile more than the table holds (flat 1024-fragment tiles)
+    big[0] = rb.RbsmJob(0x1000000, 0x20000000000, n, _p(), 0, 0x40000000000)
+    assert lib.rbsm_batch_launch_noalloc(big, 1, None, None) == -1
+    assert "tiles" in lib.rbsm_last_error().decode()
+    bad = (rb.RbsmJob * 1)()
+    bad[0] = rb.RbsmJob(0x1000000, 0x2000000, 64, p, 3, 0x3000000)
+    assert lib.rbsm_batch_launch_noalloc(bad, 1, None, None) == -1
+    t = rb.RbsmTuning(24, 1, 2048)
+    assert lib.rbsm_batch_launch_noalloc(jobs, 1, ctypes.byref(t), None) == -1
