@@ -335,35 +335,45 @@ def batched_radius_section(torch, rb, frames: int = 10):
             "bitwise_equal_to_plain": bool(equal)}
 
 
-def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: int = 4 << 30,
-                    concurrency: int = 32):
-    """Serving workload: 8 resident lights (random-triangle maps 1024^2..8192^2),
+def serving_section(torch, rb, n_requests: int = 10000, seed: int = 5001, budget: int = 4 << 30,
+                    concurrency: int = 32, loads=(0.25, 0.5, 0.75, 0.9),
+                    budgets=(768 << 20, 1 << 30, 2 << 30, 4 << 30, 8 << 30)):
+    """Serving workload: a pool of 16 resident lights (random-triangle maps,
+    four each of 1024^2, 2048^2, 4096^2 and 8192^2, rasterized on the device),
     views of 1280x720 / 1920x1080 / 3840x2160 whose light-space fragments are
-    device-resident, and requests of 1-4 distinct lights (lights 0-3 hard,
-    4-7 RSMSS r=0, equal weights) whose result is the view's composite shadow
-    buffer in device memory (where a renderer consumes it).  Compared: plain
-    per-request launches (one call per light, compositing, synchronise) vs the
-    engine (continuous batching under an HBM budget): saturation throughput
-    with `concurrency` requests outstanding, then p50/p99 latency under
-    Poisson arrivals at fractions of the plain path's saturation rate."""
+    device-resident, and n_requests requests of 1-4 distinct lights, each
+    light hard or RSMSS r=0 with equal odds, equal weights; the result is the
+    view's composite shadow buffer in device memory.  Compared: plain
+    per-request launches (one call per light, compositing, synchronise) vs
+    the engine (continuous batching under an HBM budget on the working sets
+    of admitted requests): saturation throughput with `concurrency` requests
+    outstanding, then p50/p99 latency under Poisson arrivals at fractions of
+    the plain path's saturation rate, then engine saturation across budgets."""
     import threading
     import synth
     lib = rb.load_library()
     rng = np.random.default_rng(seed)
-    sizes = [1024, 2048, 4096, 8192, 1024, 2048, 4096, 8192]
+    sizes = [1024, 2048, 4096, 8192] * 4
     views = [(1280, 720), (1920, 1080), (3840, 2160)]
     maps, frags = [], {}
     for li, S in enumerate(sizes):
         sc = synth.triangle_scene(seed * 10 + li, S, S, 64)
-        maps.append(torch.from_numpy(sc.raster()).cuda())
+        prims, rec = sc.primitives()
+        dp = torch.from_numpy(np.ascontiguousarray(prims).view(np.uint8).copy()).cuda()
+        m = torch.empty((S, S), dtype=torch.float32, device="cuda")
+        rb.rbsm_rasterize(dp, rec, S, S, out=m)
+        maps.append(m)
         for vi, (w, h) in enumerate(views):
             frags[(li, vi)] = torch.from_numpy(sc.camera_fragments(seed * 100 + 10 * li + vi, w, h)).cuda()
+    torch.cuda.synchronize()
     reqs = []
     for _ in range(n_requests):
         vi = int(rng.integers(0, 3))
         nl = int(rng.integers(1, 5))
-        reqs.append((vi, [int(x) for x in rng.choice(8, size=nl, replace=False)]))
-    evals = [views[vi][0] * views[vi][1] * len(ls) for vi, ls in reqs]
+        ls = [int(x) for x in rng.choice(16, size=nl, replace=False)]
+        modes = [int(x) for x in rng.integers(0, 2, size=nl)]
+        reqs.append((vi, ls, modes))
+    evals = np.array([views[vi][0] * views[vi][1] * len(ls) for vi, ls, _ in reqs], dtype=np.float64)
     ring = concurrency + 16
     dest = {vi: [torch.empty(w * h, dtype=torch.float32, device="cuda") for _ in range(ring)]
             for vi, (w, h) in enumerate(views)}
@@ -372,19 +382,18 @@ def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: 
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     cparams = {(li, vi): rb.Params(width=sizes[li], height=sizes[li], depth_bias=1e-4, max_dist=16,
-                                   view_width=views[vi][0]).to_c() for li in range(8) for vi in range(3)}
+                                   view_width=views[vi][0]).to_c() for li in range(16) for vi in range(3)}
 
     def plain(q, slot):
-        vi, ls = reqs[q]
+        vi, ls, modes = reqs[q]
         n = views[vi][0] * views[vi][1]
-        ptrs, modes = [], []
-        for k, li in enumerate(ls):
-            fn = lib.rbsm_visibility if li < 4 else lib.rsmss_visibility
+        ptrs = []
+        for k, (li, mode) in enumerate(zip(ls, modes)):
+            fn = lib.rbsm_visibility if mode == 0 else lib.rsmss_visibility
             st = fn(maps[li].data_ptr(), frags[(li, vi)].data_ptr(), n, ctypes.byref(cparams[(li, vi)]),
                     dev_out[k].data_ptr(), sh)
             assert st == 0, rb.rbsm_last_error()
             ptrs.append(dev_out[k].data_ptr())
-            modes.append(0 if li < 4 else 1)
         L = len(ls)
         out = dest[vi][slot % ring]
         st = lib.rbsm_composite(n, L, (ctypes.c_void_p * L)(*ptrs), (ctypes.c_int32 * L)(*modes),
@@ -393,60 +402,63 @@ def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: 
         stream.synchronize()
         return out
 
-    eng = rb.Engine(budget, concurrency)
-    ids = [eng.add_light(m) for m in maps]
+    def make_engine(b):
+        eng = rb.Engine(b, concurrency)
+        return eng, [eng.add_light(m) for m in maps]
 
-    def build(q, slot):
-        vi, ls = reqs[q]
+    def build(eng, ids, q, slot):
+        vi, ls, modes = reqs[q]
         n = views[vi][0] * views[vi][1]
-        L = [dict(light=ids[li], mode=0 if li < 4 else 1, frags=frags[(li, vi)], depth_bias=1e-4, max_dist=16,
-                  weight=1.0 / len(ls)) for li in ls]
+        L = [dict(light=ids[li], mode=mode, frags=frags[(li, vi)], depth_bias=1e-4, max_dist=16,
+                  weight=1.0 / len(ls)) for li, mode in zip(ls, modes)]
         return eng.build_request(n, L, view_width=views[vi][0], composite=dest[vi][slot % ring])[0]
 
-    built = [build(q, q) for q in range(n_requests)]  # marshalled ahead, as a native front end would
     tk = ctypes.c_int64()
 
-    def submit(q, slot):
-        req = built[q] if slot == q else build(q, slot)
+    def submit(eng, req):
         st = lib.rbsm_engine_submit(eng._h, ctypes.byref(req), ctypes.byref(tk))
         assert st == 0, rb.rbsm_last_error()
         return int(tk.value)
 
+    eng, ids = make_engine(budget)
+    built = [build(eng, ids, q, q) for q in range(n_requests)]  # marshalled ahead, as a native front end would
+
     # identical accuracy: the engine's composites equal the plain path's bitwise
     equal = True
-    for q in range(8):
+    for q in range(16):
         want = plain(q, 0).clone()
-        t = submit(q, 1)
+        t = submit(eng, build(eng, ids, q, 1))
         eng.wait(t)
         equal &= bool(torch.equal(dest[reqs[q][0]][1], want))
 
-    for q in range(4):  # warm-up
+    for q in range(32):  # warm-up
         plain(q, q)
-        eng.wait(submit(q, q))
+        eng.wait(submit(eng, built[q]))
 
-    # saturation: plain back to back; engine with `concurrency` outstanding
+    def engine_saturation(e, b_reqs):
+        busy0 = e.stats()["gpu_busy_ns"]
+        t0 = time.perf_counter()
+        pending = []
+        for q in range(n_requests):
+            if len(pending) >= concurrency:
+                lib.rbsm_engine_wait(e._h, pending.pop(0), -1, None)
+            pending.append(submit(e, b_reqs[q]))
+        for t in pending:
+            lib.rbsm_engine_wait(e._h, t, -1, None)
+        dt = time.perf_counter() - t0
+        return dt, (e.stats()["gpu_busy_ns"] - busy0) * 1e-9
+
     t0 = time.perf_counter()
     for q in range(n_requests):
         plain(q, q)
     plain_s = time.perf_counter() - t0
-    busy0 = eng.stats()["gpu_busy_ns"]
-    t0 = time.perf_counter()
-    pending = []
-    for q in range(n_requests):
-        if len(pending) >= concurrency:
-            lib.rbsm_engine_wait(eng._h, pending.pop(0), -1, None)
-        pending.append(submit(q, q))
-    for t in pending:
-        lib.rbsm_engine_wait(eng._h, t, -1, None)
-    serve_s = time.perf_counter() - t0
-    serve_gpu_ms = (eng.stats()["gpu_busy_ns"] - busy0) * 1e-6
+    serve_s, busy_s = engine_saturation(eng, built)
     plain_rate = n_requests / plain_s
-    total_evals = float(sum(evals))
+    total_evals = float(evals.sum())
 
     def poisson(frac):
         lam = frac * plain_rate
         arr = np.cumsum(rng.exponential(1.0 / lam, size=n_requests))
-        # plain: one request at a time, in arrival order
         lat_p = []
         t0 = time.perf_counter()
         for q in range(n_requests):
@@ -455,7 +467,6 @@ def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: 
                 time.sleep(arr[q] - now)
             plain(q, q)
             lat_p.append((time.perf_counter() - t0 - arr[q]) * 1e3)
-        # engine: a producer submits at the arrival times, latency from the engine
         tickets = [None] * n_requests
 
         def producer():
@@ -464,7 +475,7 @@ def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: 
                 now = time.perf_counter() - t1
                 if now < arr[q]:
                     time.sleep(arr[q] - now)
-                tickets[q] = submit(q, q)
+                tickets[q] = submit(eng, built[q])
 
         lat_s = []
         th = threading.Thread(target=producer)
@@ -479,22 +490,35 @@ def serving_section(torch, rb, n_requests: int = 300, seed: int = 5001, budget: 
                 "plain": {"p50_ms": pct(lat_p, 50), "p99_ms": pct(lat_p, 99)},
                 "engine": {"p50_ms": pct(lat_s, 50), "p99_ms": pct(lat_s, 99)}}
 
-    loads = {f"{f}x_plain_saturation": poisson(f) for f in (0.5, 0.9, 1.5)}
+    pois = {f"{f}x_plain_saturation": poisson(f) for f in loads}
     st = eng.stats()
     eng.close()
+    sweep = {}
+    for b in budgets:
+        e2, ids2 = make_engine(b)
+        b_reqs = [build(e2, ids2, q, q) for q in range(n_requests)]
+        for q in range(8):
+            e2.wait(submit(e2, b_reqs[q]))
+        dt, _ = engine_saturation(e2, b_reqs)
+        s2 = e2.stats()
+        sweep[str(b)] = {"requests_per_s": n_requests / dt, "fragments_per_s": total_evals / dt,
+                         "inflight_peak_bytes": s2["inflight_peak_bytes"], "launches": s2["launches"]}
+        e2.close()
     return {
-        "workload": "8 resident lights (maps 1024^2..8192^2, 64-triangle scenes), views 720p/1080p/4K with "
-                    f"device-resident light-space fragments, {n_requests} requests of 1-4 lights "
-                    "(lights 0-3 hard, 4-7 RSMSS r=0), composite written to a device shadow buffer",
+        "workload": "16 resident lights (4 each of 1024^2, 2048^2, 4096^2, 8192^2 maps of 64 triangles, rasterized "
+                    "on the device), views 720p/1080p/4K with device-resident light-space fragments, "
+                    f"{n_requests} requests of 1-4 lights (each hard or RSMSS r=0), composite to a device buffer",
+        "requests": n_requests,
         "fragment_evaluations": total_evals,
         "hbm_budget_bytes": budget,
         "plain_saturation": {"requests_per_s": plain_rate, "fragments_per_s": total_evals / plain_s},
         "engine_saturation": {"requests_per_s": n_requests / serve_s, "fragments_per_s": total_evals / serve_s,
-                              "outstanding": concurrency, "gpu_busy_fraction": serve_gpu_ms * 1e-3 / serve_s},
+                              "outstanding": concurrency, "gpu_busy_fraction": busy_s / serve_s},
         "speedup_vs_plain": plain_s / serve_s,
-        "poisson": loads,
+        "poisson": pois,
+        "budget_sweep": sweep,
         "engine_stats": {"launches": st["launches"], "jobs_launched": st["jobs_launched"],
-                         "arena_peak_bytes": st["arena_peak_bytes"]},
+                         "inflight_peak_bytes": st["inflight_peak_bytes"]},
         "bitwise_equal_to_plain": equal,
     }
 

@@ -310,27 +310,36 @@ int rbsm_composite(int64_t n, int32_t n_lights, const void *const *vis, const in
  * Serving engine: continuous batching of shadow requests over resident maps.
  *
  * An engine owns one device arena of hbm_budget_bytes, allocated at creation
- * (the only device allocation it makes), two streams and a scheduler thread.
- * A request is one view: its light-space fragments for 1..8 registered
- * lights (device memory, owned by the caller and left untouched until the
- * request completes), plus buffers for the results.  A result buffer in
- * device memory of the engine's device is written in place by the kernels;
- * any other (host) buffer is staged in the arena and copied back.  The engine
- * admits requests first come, first served while their staged buffers (and
- * the per-light results a composite needs) fit in the arena and fewer than
- * max_inflight requests are admitted; each scheduling step runs one batched
- * pass over the jobs of every admitted request (each per-light result is
- * bitwise the plain entry point's), the RPCF jobs, and one compositing
- * launch, then copies staged results back on a second stream while the next
- * step computes.  Requests that arrive while others run join the next step.
+ * (the only device allocation it makes), three streams (compute, upload,
+ * copy-back) and a scheduler thread.  A request is one view: its light-space
+ * fragments for 1..8 registered lights, plus buffers for the results.
+ * Fragments in device memory of the engine's device are read in place;
+ * fragments in host memory (pinned memory overlaps best) are uploaded into
+ * the arena on the upload stream while earlier steps compute.  A result
+ * buffer in device memory is written in place; a host buffer is staged in the
+ * arena and copied back on the copy stream while the next step computes.
+ *
+ * Admission (first come, first served): a request is admitted while fewer
+ * than max_inflight are, its staged buffers fit in the arena, and the HBM
+ * working sets of all admitted requests -- every light's fragments (12 B per
+ * fragment) and result (1 or 4 B), and the composite (4 B), wherever they
+ * live -- stay within hbm_budget_bytes.  Each scheduling step runs one
+ * batched pass over the jobs of every admitted request (each per-light result
+ * is bitwise the plain entry point's), the RPCF jobs, and one compositing
+ * launch.  Requests that arrive while others run join the next step.
  * Results are the same alone and in any mix.
+ *
+ * Stream order: a request's kernels wait for everything enqueued on its
+ * `stream` before the submit call (an event recorded there), so fragments
+ * and result buffers may be produced or last used asynchronously on it.
  */
 typedef struct rbsm_engine rbsm_engine;  /* opaque */
 
 typedef struct {
     int32_t light;         /* id from rbsm_engine_add_light */
     int32_t mode;          /* 0: hard (rbsm_visibility), 1: RSMSS / RPCF (rsmss_visibility) */
-    const float *frags;    /* device [3*n] light-space (u, v, z) for this light */
+    const float *frags;    /* [3*n] light-space (u, v, z) for this light: device memory
+                              (read in place) or host memory (uploaded) */
     float depth_bias;
     int32_t max_dist;      /* 1..64 */
     int32_t kernel_radius; /* mode 1 only, 0..32 */
@@ -347,6 +356,8 @@ typedef struct {
     int32_t n_lights;      /* 1..8 */
     rbsm_request_light lights[8];
     float *composite;      /* float[n] for the composite, or NULL; device or host as `out` */
+    hipStream_t stream;    /* the caller's stream that produced the device inputs and last
+                              used the device result buffers (0 = the default stream) */
 } rbsm_request;
 
 typedef struct {
@@ -355,6 +366,9 @@ typedef struct {
     int64_t fragments_completed;      /* sum over completed requests of n * n_lights */
     int64_t arena_bytes, arena_peak_bytes;
     int64_t gpu_busy_ns;              /* summed GPU time of the scheduling steps' compute */
+    int64_t inflight_bytes;           /* HBM working set of the admitted requests now */
+    int64_t inflight_peak_bytes;      /* its largest value so far (<= the budget) */
+    int64_t uploaded_bytes;           /* host fragments uploaded into the arena */
 } rbsm_engine_stats;
 
 /* Create an engine on the current device.  hbm_budget_bytes >= 4096,
@@ -367,7 +381,7 @@ int rbsm_engine_add_light(rbsm_engine *engine, const float *shadow_map, int32_t 
                           int32_t *light_id);
 
 /* Queue a request (copied; the arrays it points to are not).  Rejected when
- * its staged buffers alone exceed the budget, or a device result buffer
+ * its working set alone exceeds the budget, or a device result buffer
  * overlaps an input.  Writes a ticket. */
 int rbsm_engine_submit(rbsm_engine *engine, const rbsm_request *request, int64_t *ticket);
 
@@ -379,6 +393,13 @@ int rbsm_engine_wait(rbsm_engine *engine, int64_t ticket, int32_t timeout_ms, do
 
 int rbsm_engine_get_stats(rbsm_engine *engine, rbsm_engine_stats *stats);
 
+/* Stop serving: every queued and admitted request completes with an error
+ * (rbsm_engine_wait returns a negative code) once the work already enqueued
+ * for it has finished, so no buffer is written after its wait returns; later
+ * submissions are rejected.  For callers that must abort, and for tests of
+ * the failure path. */
+int rbsm_engine_abort(rbsm_engine *engine, const char *reason);
+
 /* Finish every queued request, stop the scheduler and free the engine. */
 void rbsm_engine_destroy(rbsm_engine *engine);
 
@@ -386,8 +407,9 @@ void rbsm_engine_destroy(rbsm_engine *engine);
 const char *rbsm_last_error(void);
 
 /* ABI version: 100 * major + minor (1.02: compositing, the serving engine and
- * rasterization; 1.03: persistent launches, walk blocking and the tuning
- * cache). */
+ * rasterization; 1.03: persistent launches, walk blocking, XCD chunking, the
+ * tuning cache, RPCF jobs in plans, the allocation-free batched pass, host
+ * fragments and producer streams in the engine, engine abort). */
 int32_t rbsm_abi_version(void);
 
 #ifdef __cplusplus

@@ -74,14 +74,15 @@ class RbsmRequestLight(ctypes.Structure):
 class RbsmRequest(ctypes.Structure):
     """Mirror of ``rbsm_request``."""
     _fields_ = [("n", ctypes.c_int64), ("view_width", ctypes.c_int32), ("n_lights", ctypes.c_int32),
-                ("lights", RbsmRequestLight * 8), ("composite", ctypes.c_void_p)]
+                ("lights", RbsmRequestLight * 8), ("composite", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
 
 
 class RbsmEngineStats(ctypes.Structure):
     """Mirror of ``rbsm_engine_stats``."""
     _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "queued", "inflight", "launches",
                                               "jobs_launched", "fragments_completed", "arena_bytes",
-                                              "arena_peak_bytes", "gpu_busy_ns")]
+                                              "arena_peak_bytes", "gpu_busy_ns", "inflight_bytes",
+                                              "inflight_peak_bytes", "uploaded_bytes")]
 
 
 class RbsmError(RuntimeError):
@@ -153,6 +154,8 @@ def load_library() -> ctypes.CDLL:
     lib.rbsm_engine_wait.restype = ctypes.c_int
     lib.rbsm_engine_get_stats.argtypes = [vp, ctypes.POINTER(RbsmEngineStats)]
     lib.rbsm_engine_get_stats.restype = ctypes.c_int
+    lib.rbsm_engine_abort.argtypes = [vp, ctypes.c_char_p]
+    lib.rbsm_engine_abort.restype = ctypes.c_int
     lib.rbsm_engine_destroy.argtypes = [vp]
     lib.rbsm_engine_destroy.restype = None
     lib.rbsm_last_error.argtypes = []
@@ -435,12 +438,14 @@ class Engine:
     requests over resident shadow maps, admitted by an HBM budget.
 
     ``submit`` takes one view: ``n`` fragments, a layout hint and 1..8
-    lights, each ``dict(light=id, mode=0|1, frags=<device float32 [n, 3]>,
+    lights, each ``dict(light=id, mode=0|1, frags=<float32 [n, 3]>,
     depth_bias=, max_dist=, kernel_radius=, weight=, out=<tensor or None>)``,
-    plus an optional float32 ``composite`` tensor.  Result tensors on the GPU
-    are written in place; host tensors (pinned, for overlap) are staged in the
-    engine's budget and copied back.  The tensors are kept alive until
-    ``wait`` returns for that ticket.
+    plus an optional float32 ``composite`` tensor.  Fragments and result
+    tensors on the GPU are used in place; host tensors (pinned, for overlap)
+    are staged in the engine's arena.  The request's kernels wait for the
+    work enqueued so far on ``stream`` (default: the current torch stream),
+    which may produce its inputs asynchronously.  The tensors are kept alive
+    until ``wait`` returns for that ticket.
     """
 
     def __init__(self, hbm_budget_bytes: int, max_inflight: int = 64):
@@ -464,9 +469,17 @@ class Engine:
         self._maps.append(shadow_map)
         return int(lid.value)
 
-    def submit(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None) -> int:
-        q, keep = self.build_request(n, lights, view_width, composite)
+    def submit(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None,
+               stream=None) -> int:
+        q, keep = self.build_request(n, lights, view_width, composite, stream)
         return self.submit_built(q, keep)
+
+    def abort(self, reason: str = "aborted by the caller") -> None:
+        """Fail every queued and admitted request (their waits raise) once the
+        work already enqueued has finished; later submissions are rejected."""
+        st = self._lib.rbsm_engine_abort(self._h, reason.encode())
+        if st != RBSM_OK:
+            raise RbsmError(rbsm_last_error())
 
     def submit_built(self, q: "RbsmRequest", keep=None) -> int:
         """Submit a request built by ``build_request`` (marshalling done ahead
@@ -478,18 +491,20 @@ class Engine:
         self._keep[int(t.value)] = keep
         return int(t.value)
 
-    def build_request(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None):
+    def build_request(self, n: int, lights: list, view_width: int = 0, composite: torch.Tensor | None = None,
+                      stream=None):
         """Marshal one request into an ``RbsmRequest``; returns it with the
         tensors that must stay alive until it completes."""
         if not 1 <= len(lights) <= 8:
             raise RbsmError("submit: need 1..8 lights")
         q = RbsmRequest()
         q.n, q.view_width, q.n_lights = int(n), int(view_width), len(lights)
+        q.stream = _stream(stream)
         keep = [composite]
         for i, L in enumerate(lights):
             f = L["frags"]
-            if f.device.type != "cuda" or f.dtype != torch.float32 or not f.is_contiguous() or f.numel() != 3 * n:
-                raise RbsmError("submit: frags must be contiguous float32 device tensors of n triples")
+            if f.dtype != torch.float32 or not f.is_contiguous() or f.numel() != 3 * n:
+                raise RbsmError("submit: frags must be contiguous float32 tensors of n triples")
             out = L.get("out")
             if out is not None:
                 want = torch.uint8 if L.get("mode", 0) == 0 else torch.float32

@@ -849,10 +849,12 @@ int rbsm_engine_create(int64_t hbm_budget_bytes, int32_t max_inflight, rbsm_engi
     rbsm_engine *E = new (std::nothrow) rbsm_engine;
     if (!E) return fail(RBSM_ERR_INVALID_ARG, "%s: out of host memory", fn);
     E->max_inflight = max_inflight;
+    E->budget = hbm_budget_bytes;
     hipError_t e = hipGetDevice(&E->device);
     if (e == hipSuccess) e = hipMalloc(&E->d_arena, (size_t)hbm_budget_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->s_compute, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->s_copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->s_upload, hipStreamNonBlocking);
     for (int s = 0; s < rbsm::kServeSlots && e == hipSuccess; ++s) {
         Slot &S = E->slots[s];
         e = hipEventCreate(&S.compute_start);
@@ -896,12 +898,17 @@ int rbsm_engine_submit(rbsm_engine *E, const rbsm_request *q, int64_t *ticket) {
     EngineReq *R = new (std::nothrow) EngineReq;
     if (!R) return fail(RBSM_ERR_INVALID_ARG, "%s: out of host memory", fn);
     R->req = *q;
-    for (int l = 0; l < q->n_lights; ++l) R->direct_out[l] = q->n > 0 && is_device_memory(q->lights[l].out, E->device);
+    for (int l = 0; l < q->n_lights; ++l) {
+        R->direct_out[l] = q->n > 0 && is_device_memory(q->lights[l].out, E->device);
+        R->host_frags[l] = q->n > 0 && q->lights[l].frags && !is_device_memory(q->lights[l].frags, E->device);
+        R->uploads = R->uploads || R->host_frags[l];
+    }
     R->direct_comp = q->n > 0 && is_device_memory(q->composite, E->device);
     R->bytes = request_bytes(*R);
-    if (R->bytes > E->stats.arena_bytes) {
+    R->work = request_work(*R);
+    if (R->work > E->budget) {
         delete R;
-        return fail(RBSM_ERR_INVALID_ARG, "%s: the request's staged results exceed the HBM budget", fn);
+        return fail(RBSM_ERR_INVALID_ARG, "%s: the request's fragments and results alone exceed the HBM budget", fn);
     }
     {
         std::lock_guard<std::mutex> lk(E->mu);
@@ -946,9 +953,19 @@ int rbsm_engine_submit(rbsm_engine *E, const rbsm_request *q, int64_t *ticket) {
             return fail(RBSM_ERR_HIP, "rbsm_engine_submit: engine failed earlier: %s", E->error.c_str());
         }
     }
-    if (hipEventCreateWithFlags(&R->done, hipEventDisableTiming) != hipSuccess) {
+    // events: results done, uploads done, and the caller's stream at submit
+    // (the engine's kernels wait for everything enqueued on it so far)
+    hipError_t ev = hipEventCreateWithFlags(&R->done, hipEventDisableTiming);
+    if (ev == hipSuccess) ev = hipEventCreateWithFlags(&R->ready, hipEventDisableTiming);
+    if (ev == hipSuccess && R->uploads) ev = hipEventCreateWithFlags(&R->uploaded, hipEventDisableTiming);
+    if (ev == hipSuccess) ev = hipEventRecord(R->ready, q->stream);
+    if (ev != hipSuccess) {
+        (void)hipGetLastError();
+        if (R->done) (void)hipEventDestroy(R->done);
+        if (R->ready) (void)hipEventDestroy(R->ready);
+        if (R->uploaded) (void)hipEventDestroy(R->uploaded);
         delete R;
-        return fail(RBSM_ERR_HIP, "%s: could not create an event", fn);
+        return fail(RBSM_ERR_HIP, "%s: could not create or record the request's events", fn);
     }
     std::lock_guard<std::mutex> lk(E->mu);
     R->t_submit = Clock::now();
@@ -978,10 +995,22 @@ int rbsm_engine_wait(rbsm_engine *E, int64_t ticket, int32_t timeout_ms, double 
     const std::string err = E->error;
     lk.unlock();
     (void)hipEventDestroy(R->done);
+    (void)hipEventDestroy(R->ready);
+    if (R->uploaded) (void)hipEventDestroy(R->uploaded);
     delete R;
     if (status < 0) return fail(RBSM_ERR_HIP, "rbsm_engine_wait: %s", err.c_str());
     if (latency_ms) *latency_ms = ms;
     return 1;
+}
+
+int rbsm_engine_abort(rbsm_engine *E, const char *reason) {
+    if (!E) return fail(RBSM_ERR_INVALID_ARG, "rbsm_engine_abort: engine is null");
+    {
+        std::lock_guard<std::mutex> lk(E->mu);
+        E->abort_reason = std::string("engine aborted: ") + (reason ? reason : "by the caller");
+    }
+    E->cv_work.notify_all();
+    return RBSM_OK;
 }
 
 int rbsm_engine_get_stats(rbsm_engine *E, rbsm_engine_stats *stats) {
@@ -1001,10 +1030,13 @@ void rbsm_engine_destroy(rbsm_engine *E) {
         E->cv_work.notify_all();
         E->worker.join();
     }
+    if (E->s_upload) (void)hipStreamSynchronize(E->s_upload);
     if (E->s_compute) (void)hipStreamSynchronize(E->s_compute);
     if (E->s_copy) (void)hipStreamSynchronize(E->s_copy);
     for (auto &kv : E->tickets) {
         (void)hipEventDestroy(kv.second->done);
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+        if (kv.second->uploaded) (void)hipEventDestroy(kv.second->uploaded);
         delete kv.second;
     }
     for (Slot &S : E->slots) {
@@ -1013,6 +1045,7 @@ void rbsm_engine_destroy(rbsm_engine *E) {
     }
     if (E->s_compute) (void)hipStreamDestroy(E->s_compute);
     if (E->s_copy) (void)hipStreamDestroy(E->s_copy);
+    if (E->s_upload) (void)hipStreamDestroy(E->s_upload);
     if (E->d_arena) (void)hipFree(E->d_arena);
     delete E;
 }

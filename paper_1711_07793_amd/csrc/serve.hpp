@@ -166,12 +166,18 @@ struct EngineReq {
     int64_t ticket = 0;
     rbsm_request req{};
     MapView maps[rbsm::kMaxLights]{};
-    int64_t off = -1, bytes = 0;         // arena block
+    int64_t off = -1, bytes = 0;         // arena block (staged fragments and results)
+    int64_t work = 0;                    // HBM working set counted against the budget
+    const float *d_frags[rbsm::kMaxLights]{};  // per-light device fragments (caller's or arena)
     void *d_out[rbsm::kMaxLights]{};     // per-light device results (caller's or arena)
     float *d_comp = nullptr;             // device composite (caller's or arena), or null
     bool direct_out[rbsm::kMaxLights]{}; // the caller's buffer is device memory: written in place
     bool direct_comp = false;
+    bool host_frags[rbsm::kMaxLights]{}; // fragments in host memory: uploaded into the arena
+    bool uploads = false;                // some fragments are uploaded
     Clock::time_point t_submit, t_done;
+    hipEvent_t ready = nullptr;          // recorded on the caller's stream at submit
+    hipEvent_t uploaded = nullptr;       // the request's uploads are in the arena
     hipEvent_t done = nullptr;           // every result is in its buffer
     int status = 0;                      // 0 pending, 1 done, < 0 failed
 };
@@ -181,14 +187,29 @@ struct Slot {
     bool busy = false;
 };
 
-// Arena bytes of a request: every per-light result not written in place, and
-// the composite when it is staged.
+// Arena bytes of a request: every per-light result not written in place, the
+// composite when it is staged, and the fragments of lights whose fragments are
+// in host memory (uploaded).
 int64_t request_bytes(const EngineReq &R) {
     const rbsm_request &r = R.req;
     int64_t b = 0;
-    for (int l = 0; l < r.n_lights; ++l)
+    for (int l = 0; l < r.n_lights; ++l) {
         if (!R.direct_out[l]) b += rbsm::Arena::round_up(r.n * (r.lights[l].mode == 0 ? 1 : 4));
+        if (R.host_frags[l]) b += rbsm::Arena::round_up(r.n * 12);
+    }
     if (r.composite && !R.direct_comp) b += rbsm::Arena::round_up(r.n * 4);
+    return b;
+}
+
+// HBM working set of a request while it is admitted: its fragments (12 B per
+// fragment and light) and its results (1 or 4 B per fragment and light, 4 B
+// for the composite), wherever they live.  Admission keeps the sum over
+// admitted requests within the budget.
+int64_t request_work(const EngineReq &R) {
+    const rbsm_request &r = R.req;
+    int64_t b = 0;
+    for (int l = 0; l < r.n_lights; ++l) b += r.n * (12 + (r.lights[l].mode == 0 ? 1 : 4));
+    if (r.composite) b += r.n * 4;
     return b;
 }
 
@@ -210,7 +231,9 @@ struct rbsm_engine {
     char *d_arena = nullptr;
     rbsm::Arena arena;  // worker thread only
     int32_t max_inflight = 1;
-    hipStream_t s_compute = nullptr, s_copy = nullptr;
+    int64_t budget = 0;       // HBM budget of the admitted requests' working sets
+    int64_t work = 0;         // their current sum (worker thread only)
+    hipStream_t s_compute = nullptr, s_copy = nullptr, s_upload = nullptr;
     Slot slots[rbsm::kServeSlots];
 
     std::mutex mu;  // guards everything below
@@ -221,6 +244,7 @@ struct rbsm_engine {
     int64_t next_ticket = 1;
     bool stop = false;
     std::string error;
+    std::string abort_reason;  // set by rbsm_engine_abort, acted on by the worker
     rbsm_engine_stats stats{};
 
     std::vector<EngineReq *> admitted;  // worker thread only
@@ -244,14 +268,33 @@ int pick_slot(rbsm_engine *E) {
 }  // namespace
 
 void rbsm_engine::fail_all(const char *what, hipError_t e) {
+    // work already enqueued may still write the callers' buffers (host
+    // copies included): let it finish before anyone learns of the failure
+    (void)hipStreamSynchronize(s_upload);
+    (void)hipStreamSynchronize(s_compute);
+    (void)hipStreamSynchronize(s_copy);
+    (void)hipGetLastError();
+    for (int s = 0; s < rbsm::kServeSlots; ++s) slots[s].busy = false;
     std::lock_guard<std::mutex> lk(mu);
-    if (error.empty()) error = std::string(what) + ": " + hipGetErrorString(e);
-    for (auto *r : admitted) r->status = RBSM_ERR_HIP;
-    for (auto *r : inflight) r->status = RBSM_ERR_HIP;
-    for (auto *r : queue) r->status = RBSM_ERR_HIP;
-    admitted.clear();
-    inflight.clear();
+    if (error.empty()) error = e == hipSuccess ? std::string(what) : std::string(what) + ": " + hipGetErrorString(e);
+    const Clock::time_point now = Clock::now();
+    for (std::vector<EngineReq *> *list : {&admitted, &inflight}) {
+        for (auto *r : *list) {
+            if (r->bytes > 0 && r->off >= 0) arena.release(r->off, r->bytes);
+            r->status = RBSM_ERR_HIP;
+            r->t_done = now;
+            stats.inflight -= 1;
+        }
+        list->clear();
+    }
+    for (auto *r : queue) {
+        r->status = RBSM_ERR_HIP;
+        r->t_done = now;
+        stats.queued -= 1;
+    }
     queue.clear();
+    work = 0;
+    stats.inflight_bytes = 0;
     cv_done.notify_all();
 }
 
@@ -290,7 +333,13 @@ bool rbsm_engine::step_launch() {
     if (batch.empty()) return false;
     admitted.erase(admitted.begin(), admitted.begin() + taken);
 
-    hipError_t e = hipEventRecord(S.compute_start, s_compute);
+    hipError_t e = hipSuccess;
+    // the callers' producer streams and the fragment uploads come first
+    for (EngineReq *R : batch) {
+        if (e == hipSuccess) e = hipStreamWaitEvent(s_compute, R->ready, 0);
+        if (e == hipSuccess && R->uploads) e = hipStreamWaitEvent(s_compute, R->uploaded, 0);
+    }
+    if (e == hipSuccess) e = hipEventRecord(S.compute_start, s_compute);
     const size_t lds = (size_t)kDefaultTile.cap * sizeof(float);
     // tile jobs of both modes, in chunks that fit the kernel arguments
     {
@@ -306,7 +355,7 @@ bool rbsm_engine::step_launch() {
                 if (lay.tiles == 0) continue;
                 JobDev &D = A.jobs[A.n_jobs];
                 D.m = R->maps[list[c].second];
-                D.frags = L.frags;
+                D.frags = R->d_frags[list[c].second];
                 D.out = R->d_out[list[c].second];
                 D.n = q.n;
                 D.vw = lay.vw;
@@ -315,7 +364,7 @@ bool rbsm_engine::step_launch() {
                 D.bias = L.depth_bias;
                 D.maxd = L.max_dist;
                 D.mode = L.mode;
-                D.vec_ok = ((uintptr_t)L.frags % 16 == 0) && ((uintptr_t)D.out % (L.mode == 0 ? 4 : 16) == 0) &&
+                D.vec_ok = ((uintptr_t)D.frags % 16 == 0) && ((uintptr_t)D.out % (L.mode == 0 ? 4 : 16) == 0) &&
                            (lay.vw % 4 == 0);
                 A.first[A.n_jobs++] = tiles;
                 tiles += lay.tiles;
@@ -329,8 +378,8 @@ bool rbsm_engine::step_launch() {
         const rbsm_request &q = rj.first->req;
         const rbsm_request_light &L = q.lights[rj.second];
         if (q.n == 0) continue;
-        launch_rpcf(rj.first->maps[rj.second], L.frags, q.n, q.view_width, L.depth_bias, L.max_dist, L.kernel_radius,
-                    static_cast<float *>(rj.first->d_out[rj.second]), s_compute);
+        launch_rpcf(rj.first->maps[rj.second], rj.first->d_frags[rj.second], q.n, q.view_width, L.depth_bias,
+                    L.max_dist, L.kernel_radius, static_cast<float *>(rj.first->d_out[rj.second]), s_compute);
     }
     for (size_t c0 = 0; c0 < comps.size(); c0 += rbsm::kArgComp) {
         rbsm::CompArgs A{};
@@ -372,8 +421,19 @@ bool rbsm_engine::step_launch() {
 void rbsm_engine::run() {
     (void)hipSetDevice(device);
     Clock::time_point idle_since{};
+    hipError_t upload_error = hipSuccess;
     for (;;) {
         bool progress = false;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (!abort_reason.empty()) {
+                const std::string why = abort_reason;
+                abort_reason.clear();
+                lk.unlock();
+                fail_all(why.c_str(), hipSuccess);
+                continue;
+            }
+        }
         // steps whose compute finished free their table slot
         for (int s = 0; s < rbsm::kServeSlots; ++s) {
             if (!slots[s].busy) continue;
@@ -400,7 +460,9 @@ void rbsm_engine::run() {
                 continue;
             }
             if (R->bytes > 0) arena.release(R->off, R->bytes);
+            work -= R->work;
             std::lock_guard<std::mutex> lk(mu);
+            stats.inflight_bytes = work;
             R->t_done = Clock::now();
             R->status = q == hipSuccess ? 1 : RBSM_ERR_HIP;
             if (q != hipSuccess && error.empty()) error = std::string("engine: copy: ") + hipGetErrorString(q);
@@ -417,27 +479,53 @@ void rbsm_engine::run() {
             std::lock_guard<std::mutex> lk(mu);
             while (!queue.empty() && (int64_t)(admitted.size() + inflight.size()) < max_inflight) {
                 EngineReq *R = queue.front();
+                if (work + R->work > budget) break;  // the working sets stay within the HBM budget
                 const int64_t off = R->bytes > 0 ? arena.alloc(R->bytes) : 0;  // nothing staged: no block
                 if (off < 0) break;
                 R->off = off;
                 char *p = d_arena + off;
+                const int64_t n = R->req.n;
+                hipError_t e = hipSuccess;
                 for (int l = 0; l < R->req.n_lights; ++l) {
+                    if (R->host_frags[l]) {  // uploaded on the upload stream while earlier steps compute
+                        R->d_frags[l] = reinterpret_cast<const float *>(p);
+                        if (e == hipSuccess)
+                            e = hipMemcpyAsync(p, R->req.lights[l].frags, (size_t)n * 12, hipMemcpyHostToDevice,
+                                               s_upload);
+                        p += rbsm::Arena::round_up(n * 12);
+                        stats.uploaded_bytes += n * 12;
+                    } else {
+                        R->d_frags[l] = R->req.lights[l].frags;
+                    }
                     if (R->direct_out[l]) {
                         R->d_out[l] = R->req.lights[l].out;
                         continue;
                     }
                     R->d_out[l] = p;
-                    p += rbsm::Arena::round_up(R->req.n * (R->req.lights[l].mode == 0 ? 1 : 4));
+                    p += rbsm::Arena::round_up(n * (R->req.lights[l].mode == 0 ? 1 : 4));
                 }
                 R->d_comp = R->direct_comp ? R->req.composite
                                            : (R->req.composite ? reinterpret_cast<float *>(p) : nullptr);
+                if (e == hipSuccess && R->uploads) e = hipEventRecord(R->uploaded, s_upload);
+                work += R->work;
+                stats.inflight_bytes = work;
+                stats.inflight_peak_bytes = std::max(stats.inflight_peak_bytes, work);
                 queue.pop_front();
                 admitted.push_back(R);
                 stats.queued -= 1;
                 stats.inflight += 1;
                 stats.arena_peak_bytes = arena.peak();
                 progress = true;
+                if (e != hipSuccess) {  // the request holds its block and budget: fail_all releases them
+                    upload_error = e;
+                    break;
+                }
             }
+        }
+        if (upload_error != hipSuccess) {
+            fail_all("engine: fragment upload", upload_error);
+            upload_error = hipSuccess;
+            continue;
         }
         if (step_launch()) progress = true;
         if (!progress) {
@@ -450,7 +538,7 @@ void rbsm_engine::run() {
             }
             std::unique_lock<std::mutex> lk(mu);
             if (stop && queue.empty()) break;
-            if (!queue.empty()) continue;
+            if (!queue.empty() || !abort_reason.empty()) continue;
             // idle: keep polling for a short while (a request arriving now is
             // picked up at once), then sleep until a submission
             const auto now = Clock::now();
@@ -460,7 +548,7 @@ void rbsm_engine::run() {
                 std::this_thread::yield();
                 continue;
             }
-            cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+            cv_work.wait(lk, [&] { return stop || !queue.empty() || !abort_reason.empty(); });
             idle_since = Clock::time_point{};
         }
     }

@@ -667,10 +667,11 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 }
 
 // The same pass with resident workgroups looping over the tiles (the job is
-// the kernel argument; tile_base 0).  The prefetched fragments take 12 more
-// VGPRs, so the kernel runs at up to 80 (6 waves per SIMD).
+// the kernel argument; tile_base 0).  The prefetched fragments and the loop
+// need more registers than a one-shot tile: at 80 the loop spills, so the
+// kernel runs at up to 96 VGPRs (5 waves per SIMD, 5 workgroups per CU).
 template <bool HARD, int TW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(6, 6))) void tile_persistent_kernel(
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5, 5))) void tile_persistent_kernel(
     const JobDev J, int64_t tiles, int apron, int cap) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
@@ -696,9 +697,10 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 
 // Batched pass with resident workgroups looping over the tiles of every job,
 // the next tile's job and fragments read while the current tile is worked on;
-// WF and WB are the walk blocking the autotuner searches.
+// WF and WB are the walk blocking the autotuner searches.  Up to 96 VGPRs (5
+// workgroups per CU), as tile_persistent_kernel.
 template <int TW, int WF, int WB>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(6, 6))) void batch_persistent_kernel(
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5, 5))) void batch_persistent_kernel(
     const JobDev *__restrict__ jobs, const uint16_t *__restrict__ block_job, int64_t tiles, int apron, int cap) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;

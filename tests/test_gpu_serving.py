@@ -74,22 +74,24 @@ def _outs(world, req, where="pinned"):
     return n, w, outs, buf(torch.float32)
 
 
-def _submit(eng, ids, world, req, outs, comp):
+def _submit(eng, ids, world, req, outs, comp, host_frags=None):
     w, h = world["views"][req["view"]]
     lights = []
     for L, o in zip(req["lights"], outs):
-        lights.append(dict(L, light=ids[L["light"]], frags=world["dev_frags"][(L["light"], req["view"])], out=o))
+        f = world["dev_frags"][(L["light"], req["view"])] if host_frags is None else \
+            host_frags[(L["light"], req["view"])]
+        lights.append(dict(L, light=ids[L["light"]], frags=f, out=o))
     return eng.submit(w * h, lights, view_width=w, composite=comp)
 
 
-def _run(rb, world, budget, max_inflight, burst, where="pinned"):
+def _run(rb, world, budget, max_inflight, burst, where="pinned", host_frags=None):
     eng = rb.Engine(budget, max_inflight)
     ids = [eng.add_light(m) for m in world["dev_maps"]]
     results = []
     tickets = []
     for req in world["reqs"]:
         n, w, outs, comp = _outs(world, req, where)
-        t = _submit(eng, ids, world, req, outs, comp)
+        t = _submit(eng, ids, world, req, outs, comp, host_frags)
         if burst:
             tickets.append(t)
         else:
@@ -164,10 +166,11 @@ def test_alone_and_in_the_mix_are_identical(rb, world):
     # a budget that holds only a few requests' results at a time forces
     # admission waits, several requests per step and overlapping steps
     say("serving: mix")
-    mix, st_m = _run(rb, world, budget=2 << 20, max_inflight=6, burst=True)
+    mix, st_m = _run(rb, world, budget=6 << 20, max_inflight=6, burst=True)
     assert st_a["completed"] == st_m["completed"] == len(world["reqs"])
     assert st_m["launches"] < len(world["reqs"])          # requests were batched together
     assert st_m["arena_peak_bytes"] <= st_m["arena_bytes"]
+    assert 0 < st_m["inflight_peak_bytes"] <= 6 << 20        # working sets held within the budget
     for k, ((oa, ca), (om, cm)) in enumerate(zip(alone, mix)):
         for x, y in zip(oa, om):
             assert np.array_equal(x, y), k
@@ -175,9 +178,9 @@ def test_alone_and_in_the_mix_are_identical(rb, world):
     # results written in place on the device (no staging) and to pageable host
     # memory: the same values again
     say("serving: device and pageable destinations")
-    dev, st_d = _run(rb, world, budget=1 << 20, max_inflight=6, burst=True, where="device")
+    dev, st_d = _run(rb, world, budget=5 << 20, max_inflight=6, burst=True, where="device")
     assert st_d["arena_peak_bytes"] == 0                  # nothing staged
-    page, _ = _run(rb, world, budget=2 << 20, max_inflight=6, burst=True, where="pageable")
+    page, _ = _run(rb, world, budget=6 << 20, max_inflight=6, burst=True, where="pageable")
     for k in range(len(alone)):
         for x, y, z in zip(alone[k][0], dev[k][0], page[k][0]):
             assert np.array_equal(x, y) and np.array_equal(x, z), k
@@ -337,3 +340,96 @@ def test_full_size_requests_sampled_against_oracle(rb):
         tol = SOFT_TOL * sum(L["weight"] for L in lights) + 1e-6
         assert np.max(np.abs(comp.cpu().numpy()[idx].astype(np.float64) - wc)) <= tol, vi
     eng.close()
+
+
+def test_host_fragments_uploaded_under_a_tight_budget(rb, world):
+    """Fragments in pinned host memory are uploaded into the engine's arena; a
+    budget of about 1.5 of the largest request's working set makes requests
+    wait for earlier ones' fragments and results to leave before theirs are
+    uploaded.  Every result equals the device-resident run, bitwise."""
+    say("serving: device-resident fragments")
+    ref, _ = _run(rb, world, budget=256 << 20, max_inflight=8, burst=True)
+    host = {k: torch.from_numpy(v.copy()).pin_memory() for k, v in world["frags"].items()}
+    say("serving: host fragments, tight budget")
+    got, st = _run(rb, world, budget=6 << 20, max_inflight=8, burst=True, host_frags=host)
+    assert st["completed"] == len(world["reqs"])
+    assert st["uploaded_bytes"] == sum(12 * world["views"][r["view"]][0] * world["views"][r["view"]][1] *
+                                       len(r["lights"]) for r in world["reqs"])
+    assert 0 < st["inflight_peak_bytes"] <= 6 << 20
+    for k in range(len(ref)):
+        for x, y in zip(ref[k][0], got[k][0]):
+            assert np.array_equal(x, y), k
+        assert np.array_equal(ref[k][1], got[k][1]), k
+    # pageable host fragments: the same
+    page = {k: torch.from_numpy(v.copy()) for k, v in world["frags"].items()}
+    got2, _ = _run(rb, world, budget=6 << 20, max_inflight=4, burst=True, where="device", host_frags=page)
+    for k in range(len(ref)):
+        for x, y in zip(ref[k][0], got2[k][0]):
+            assert np.array_equal(x, y), k
+
+
+def test_requests_wait_for_their_producer_stream(rb, world):
+    """Fragments and output buffers produced asynchronously on a side stream:
+    the request's kernels wait for that stream's work before the submit."""
+    eng = rb.Engine(256 << 20, 8)
+    ids = [eng.add_light(m) for m in world["dev_maps"]]
+    side = torch.cuda.Stream()
+    big = torch.randn(4096, 4096, device="cuda")
+    for req in world["reqs"][:6]:
+        w, h = world["views"][req["view"]]
+        n = w * h
+        with torch.cuda.stream(side):
+            busy = big @ big                       # keeps the side stream busy a while
+            lights, outs = [], []
+            for L in req["lights"]:
+                src = world["dev_frags"][(L["light"], req["view"])]
+                f = torch.empty_like(src)
+                f.copy_(src)                       # produced on the side stream
+                o = torch.full((n,), 3 if L["mode"] == 0 else -3.0,
+                               dtype=torch.uint8 if L["mode"] == 0 else torch.float32, device="cuda")
+                outs.append(o)
+                lights.append(dict(L, light=ids[L["light"]], frags=f, out=o))
+        t = eng.submit(n, lights, view_width=w, stream=side)
+        assert eng.wait(t, 60000) is not None
+        del busy
+        po, _ = _plain(rb, world, req)
+        for x, y in zip(outs, po):
+            assert np.array_equal(x.cpu().numpy(), y)
+    eng.close()
+
+
+def test_abort_fails_pending_requests_cleanly(rb, world):
+    """rbsm_engine_abort (forced from the host; every kernel runs normally):
+    each wait returns (done before the abort, or an error after the work
+    already enqueued finished), the counters drain, later submissions are
+    rejected, and the engine closes."""
+    eng = rb.Engine(6 << 20, 2)
+    ids = [eng.add_light(m) for m in world["dev_maps"]]
+    bufs = [_outs(world, req, "device") for req in world["reqs"]]
+    side = torch.cuda.Stream()
+    big = torch.randn(4096, 4096, device="cuda")
+    with torch.cuda.stream(side):
+        for _ in range(12):                # the requests' producer stream stays busy a while
+            big = big @ big / 4096.0
+    tickets = []
+    for req, (n, w, outs, comp) in zip(world["reqs"], bufs):
+        lights = [dict(L, light=ids[L["light"]], frags=world["dev_frags"][(L["light"], req["view"])], out=o)
+                  for L, o in zip(req["lights"], outs)]
+        tickets.append(eng.submit(n, lights, view_width=w, composite=comp, stream=side))
+    eng.abort("test")
+    done = failed = 0
+    for t in tickets:
+        try:
+            assert eng.wait(t, 60000) is not None
+            done += 1
+        except rb.RbsmError as e:
+            assert "aborted" in str(e)
+            failed += 1
+    assert done + failed == len(tickets) and failed > 0
+    st = eng.stats()
+    assert st["queued"] == 0 and st["inflight"] == 0 and st["inflight_bytes"] == 0
+    n, w, outs, comp = _outs(world, world["reqs"][0], "device")
+    with pytest.raises(rb.RbsmError):
+        _submit(eng, ids, world, world["reqs"][0], outs, comp)
+    eng.close()
+    side.synchronize()
