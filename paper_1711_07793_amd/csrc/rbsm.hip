@@ -302,7 +302,8 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
 
 // The batched kernel instance of a tuning: one workgroup per tile
 // (batch_kernel) or resident workgroups looping over tiles
-// (batch_persistent_kernel, built for every walk blocking the tuner tries).
+// (batch_persistent_kernel), each built for every walk blocking the tuner
+// tries.
 template <int TW>
 const void *persistent_instance(int wf, int wb) {
     if (wb == 8) {
@@ -315,12 +316,24 @@ const void *persistent_instance(int wf, int wb) {
     return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 2, 4>);
 }
 
+template <int TW>
+const void *oneshot_instance(int wf, int wb) {
+    if (wb == 8) {
+        if (wf == 1) return reinterpret_cast<const void *>(&batch_kernel<TW, 1, 8>);
+        if (wf == 4) return reinterpret_cast<const void *>(&batch_kernel<TW, 4, 8>);
+        return reinterpret_cast<const void *>(&batch_kernel<TW, 2, 8>);
+    }
+    if (wf == 1) return reinterpret_cast<const void *>(&batch_kernel<TW, 1, 4>);
+    if (wf == 4) return reinterpret_cast<const void *>(&batch_kernel<TW, 4, 4>);
+    return reinterpret_cast<const void *>(&batch_kernel<TW, 2, 4>);
+}
+
 const void *batch_instance(const rbsm_tuning &t) {
     const int wf = t.walk_first ? t.walk_first : kWalkFirst, wb = t.walk_block ? t.walk_block : kWalkSteps;
     if (!t.persistent) {
-        if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_kernel<16>);
-        if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_kernel<64>);
-        return reinterpret_cast<const void *>(&batch_kernel<32>);
+        if (t.tile_w == 16) return oneshot_instance<16>(wf, wb);
+        if (t.tile_w == 64) return oneshot_instance<64>(wf, wb);
+        return oneshot_instance<32>(wf, wb);
     }
     if (t.tile_w == 16) return persistent_instance<16>(wf, wb);
     if (t.tile_w == 64) return persistent_instance<64>(wf, wb);
@@ -679,7 +692,7 @@ int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_
     };
     // coordinate search: tile shape and schedule, then (one workgroup per
     // tile) how tiles are dealt to XCDs, then LDS capacity, then apron, then
-    // (persistent launches) the walk blocking
+    // the walk blocking
     rbsm_tuning base = rbsm_default_tuning();
     for (int tw : {16, 32, 64})
         for (int per : {0, 1}) {
@@ -708,8 +721,7 @@ int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_
         trial(c);
     }
     base = best;
-    if (base.persistent)
-        for (int wf : {1, 2, 4})
+    for (int wf : {1, 2, 4})
             for (int wb : {4, 8}) {
                 if (wf == base.walk_first && wb == base.walk_block) continue;
                 rbsm_tuning c = base;

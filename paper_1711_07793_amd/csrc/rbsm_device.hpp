@@ -34,6 +34,12 @@ template <class T>
 __device__ __forceinline__ void gst(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
 }
+// 12-byte loads (three consecutive texels, 4-byte aligned) through a native
+// vector type whose alignment is lowered to 4, so the load is exactly 12 bytes.
+typedef float f32x3 __attribute__((ext_vector_type(3), aligned(4)));
+__device__ __forceinline__ f32x3 gld3(const float *p) {
+    return *(const __attribute__((address_space(1))) f32x3 *)p;
+}
 // 16-byte forms through a native vector type (HIP's float4 is a class whose
 // copy takes a generic reference, which would bring the flat access back).
 typedef float f32x4 __attribute__((ext_vector_type(4)));

@@ -386,9 +386,21 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                 const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
                 if (off32) {  // 32-bit byte offsets from the map's base
                     const unsigned row = (unsigned)tj * pitch4;
-                    tc[f][0] = gld((const float *)(base8 + (row + 4u * (unsigned)il)));
-                    tc[f][1] = gld((const float *)(base8 + (row + 4u * (unsigned)ti)));
-                    tc[f][2] = gld((const float *)(base8 + (row + 4u * (unsigned)ir)));
+                    // left, centre and right in one 12-byte load (the clamped
+                    // triple starts at column il; at the map's left or right
+                    // edge the centre or the right texel is the clamp)
+                    const unsigned c3 = (unsigned)min(il, max(m.W - 3, 0));
+                    if (m.W >= 3) {
+                        const f32x3 t3 = gld3((const float *)(base8 + (row + 4u * c3)));
+                        const int sc = ti - (int)c3;  // 0 (ti = 0), 1, or 2 (ti = W-1)
+                        tc[f][0] = sc == 2 ? t3.y : t3.x;
+                        tc[f][1] = sc == 0 ? t3.x : (sc == 1 ? t3.y : t3.z);
+                        tc[f][2] = sc == 0 ? t3.y : t3.z;
+                    } else {
+                        tc[f][0] = gld((const float *)(base8 + (row + 4u * (unsigned)il)));
+                        tc[f][1] = gld((const float *)(base8 + (row + 4u * (unsigned)ti)));
+                        tc[f][2] = gld((const float *)(base8 + (row + 4u * (unsigned)ir)));
+                    }
                     tc[f][3] = gld((const float *)(base8 + ((unsigned)jh * pitch4 + 4u * (unsigned)ti)));
                     tc[f][4] = gld((const float *)(base8 + ((unsigned)jl * pitch4 + 4u * (unsigned)ti)));
                 } else {
@@ -681,8 +693,9 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5, 5))) void
 // Batched pass: one workgroup per tile of any job; block_job maps the
 // (XCD-ordered) workgroup index to its job.  Each tile runs the steps of the
 // single-view pass, so every output is bitwise the same; the mode is a
-// per-workgroup value, so one code path serves both and fits 64 VGPRs.
-template <int TW>
+// per-workgroup value, so one code path serves both and fits 64 VGPRs.  WF
+// and WB are the walk blocking the autotuner searches.
+template <int TW, int WF = kWalkFirst, int WB = kWalkSteps>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_kernel(const JobDev *__restrict__ jobs,
                                                    const uint16_t *__restrict__ block_job, int apron, int cap,
                                                    int chunk_log2) {
@@ -691,8 +704,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, chunk_log2);
     const JobDev J = jobs[block_job[g]];
     const int64_t tile = g - J.tile_base;
-    process_tile<2, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out, tile, sh,
-                        s_tex, J.mode == 0);
+    process_tile<2, TW, WF, WB>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out, tile,
+                                sh, s_tex, J.mode == 0);
 }
 
 // Batched pass with resident workgroups looping over the tiles of every job,
@@ -765,9 +778,33 @@ void launch_tiles(const MapView &mv, const float *frags, int64_t n, int64_t vw, 
     }
 }
 
+// Flat launches of few fragments (no screen layout): one lane per fragment,
+// its five texels and its walks read from global memory (L2), the listing's
+// steps per fragment (eval_texel), so every result equals the tile pass's.
+// 1024-fragment tiles would leave most CUs idle (65,536 fragments make 64
+// workgroups), and the texel box of scattered fragments spans the whole map,
+// so staging would not happen anyway.
+constexpr int64_t kFlatFragMax = (int64_t)1 << 20;
+
+template <bool HARD>
+__global__ __launch_bounds__(256) void frag_kernel(MapView m, const float *__restrict__ frags, int64_t n, float bias,
+                                                   int maxd, void *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const Addr a = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), gld(frags + 3 * k + 2), m.W, m.H, bias);
+    const float v = eval_texel<HARD>(m, a.i0, a.j0, a.fx, a.fy, a.zb, maxd);
+    if (HARD) gst(static_cast<uint8_t *>(out) + k, (uint8_t)(v != 0.0f ? 1 : 0));
+    else gst(static_cast<float *>(out) + k, v);
+}
+
 template <bool HARD>
 void launch_pass(const MapView &mv, const float *frags, int64_t n, int64_t view_width, float bias, int maxd,
                  TileConfig cfg, void *out, size_t out_align, hipStream_t stream) {
+    if (view_width <= 0 && n <= kFlatFragMax) {
+        hipLaunchKernelGGL((frag_kernel<HARD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, mv, frags, n,
+                           bias, maxd, out);
+        return;
+    }
     int64_t vw = view_width;
     int tw = cfg.tile_w;
     if (vw <= 0) {  // flat: one row of n pixels, 1024-fragment chunks
