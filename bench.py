@@ -71,11 +71,16 @@ def tuning_label(t: dict) -> str:
                                             "xcd_chunk"))
 
 
-def kernel_instance(t: dict) -> str:
-    """Name of the batched kernel a tuning launches."""
+ARG_JOBS_MAX = 48  # jobs with tiles whose records a one-shot launch takes in its kernel arguments
+
+
+def kernel_instance(t: dict, tiled_jobs: int) -> str:
+    """Name of the batched kernel a tuning launches for a plan with
+    `tiled_jobs` jobs in the tile pass."""
     if t["persistent"]:
         return f"batch_persistent_kernel<{t['tile_w']}, {t['walk_first']}, {t['walk_block']}>"
-    return f"batch_kernel<{t['tile_w']}>"
+    name = "batch_arg_kernel" if tiled_jobs <= ARG_JOBS_MAX else "batch_kernel"
+    return f"{name}<{t['tile_w']}, {t['walk_first']}, {t['walk_block']}>"
 
 
 class Frames:
@@ -203,6 +208,9 @@ class BatchedFrame:
             self.jobs.append(dict(map=self.maps[j["map"]], frags=f, params=params, mode=j["mode"], out=out))
         self.radii = radii
         self.n_frag = sum(j["frags"].numel() // 3 for j in self.jobs)
+        # jobs in the tile pass (RPCF jobs run their own kernel)
+        self.tiled_jobs = sum(1 for j in self.jobs if j["frags"].numel() > 0 and
+                              not (j["mode"] == 1 and j["params"].get("kernel_radius", 0) > 0))
         self.resident_bytes = sum(t.numel() * t.element_size() for t in self.maps) + sum(
             j["frags"].numel() * 4 + j["out"].numel() * j["out"].element_size() for j in self.jobs)
         lib = rb.load_library()
@@ -743,6 +751,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--section", choices=["single_view_hard", "rsmss", "uniform_512", "serving"],
+                    help="run only this extra section (for profiling) and print it as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -755,6 +765,21 @@ def main():
 
     rb.load_library()
     torch.cuda.init()
+
+    if args.section:
+        out = {}
+        if args.copy_calibration:
+            out["copy_kernel_GBps"] = copy_bandwidth(torch)
+        if args.section == "single_view_hard":
+            out[args.section] = single_view_section(torch, rb, args.steps)
+        elif args.section == "rsmss":
+            out.update(rsmss_section(torch, rb, args.steps))
+        elif args.section == "uniform_512":
+            out[args.section] = uniform_section(torch, rb, args.steps)
+        else:
+            out[args.section] = serving_section(torch, rb)
+        print(json.dumps(out), flush=True)
+        return
 
     # ---- headline: the batched workload, one graph replay per step --------
     bf = BatchedFrame(torch, rb)
@@ -793,7 +818,7 @@ def main():
         "p99_frame_ms": h["p99_frame_ms"],
         "bitwise_equal_to_plain": h["bitwise_equal_to_plain"],
         "roofline": {
-            "kernel": kernel_instance(tune) + " (batched plan, graph replay)",
+            "kernel": kernel_instance(tune, bf.tiled_jobs) + " (batched plan, graph replay)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBPS,

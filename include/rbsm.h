@@ -140,7 +140,8 @@ typedef struct {
     int32_t walk_first; /* traversal steps every walk takes before unfinished
                            walks are regrouped: 1, 2 or 4 (0 = default 2) */
     int32_t walk_block; /* steps per block of a regrouped walk, read together:
-                           4 or 8 (0 = default 4) */
+                           4 or 8 (0 = default 4); with persistent = 1 both
+                           walk fields must be 0 or their defaults */
     int32_t xcd_chunk;  /* how tiles are dealt to the 8 XCDs: -1 one contiguous
                            range each; c in 0..12: chunks of 2^c consecutive
                            tiles round-robin (balances uneven jobs) */
@@ -199,7 +200,7 @@ int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream);
  * stream with HIP events and keeps the fastest, searching one axis after the
  * other: tile width x launch form (one workgroup per tile or persistent),
  * then (one workgroup per tile) the XCD chunking, then LDS capacity, then
- * apron, then the walk blocking.  The
+ * apron, then (one workgroup per tile) the walk blocking.  The
  * choice is cached in the process under a key of the device (architecture,
  * CU count) and the plan's job layout (per job: fragments, view width, map
  * size and pitch, MAXDIST, mode); a later call with the same key applies the

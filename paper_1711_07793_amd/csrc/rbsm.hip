@@ -175,7 +175,9 @@ struct rbsm_plan {
     uint16_t *d_block_job = nullptr;
     int64_t blocks = 0;
     int64_t grid = 0;  // workgroups of a persistent launch (resident ones, at most blocks)
-    std::vector<int32_t> rpcf_jobs;  // jobs with kernel_radius > 0, launched after the tile pass
+    std::vector<int32_t> rpcf_jobs;  // jobs with kernel_radius > 0, launched before the tile pass
+    BatchArgs args{};                // the tile-pass jobs as kernel arguments (when use_args)
+    bool use_args = false;
     int64_t fragments = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -206,10 +208,41 @@ int64_t plan_grid(const rbsm_plan *p);
 // job and every overlap.
 struct HostTables {
     std::vector<JobDev> dev;
+    std::vector<int64_t> job_tiles;  // tiles of each job in the tile pass (0 for RPCF and empty jobs)
     std::vector<uint16_t> block_job;
     std::vector<int32_t> rpcf;
     int64_t tiles = 0, frags = 0;
 };
+
+// The jobs with tiles as kernel-argument records, when there are at most
+// kArgJobsMax of them and every pitch fits 32 bits.
+bool make_args(const HostTables &T, BatchArgs *a) {
+    int k = 0;
+    for (size_t j = 0; j < T.dev.size(); ++j) {
+        if (T.job_tiles[j] == 0) continue;
+        const JobDev &D = T.dev[j];
+        if (k == kArgJobsMax || D.m.pitch > (int64_t)INT32_MAX) return false;
+        JobArg &A = a->jobs[k];
+        A.t = D.m.t;
+        A.frags = D.frags;
+        A.out = D.out;
+        A.pitch = (int32_t)D.m.pitch;
+        A.W = D.m.W;
+        A.H = D.m.H;
+        A.n = (int32_t)D.n;
+        A.vw = (int32_t)D.vw;
+        A.tiles_x = (int32_t)D.tiles_x;
+        A.tile_base = (int32_t)D.tile_base;
+        A.bias = D.bias;
+        A.maxd = (int16_t)D.maxd;
+        A.vec_ok = (uint8_t)D.vec_ok;
+        A.mode = (uint8_t)D.mode;
+        a->first[k] = (int32_t)D.tile_base;
+        ++k;
+    }
+    for (int r = k; r < kArgJobsMax; ++r) a->first[r] = INT32_MAX;
+    return k > 0;
+}
 
 int make_tables(const char *fn, const rbsm_job *jobs, int32_t n_jobs, int tile_w, const std::vector<rbsm_job> *same_layout,
                 bool want_map, HostTables &T) {
@@ -217,6 +250,7 @@ int make_tables(const char *fn, const rbsm_job *jobs, int32_t n_jobs, int tile_w
     if (same_layout && (size_t)n_jobs != same_layout->size())
         return fail(RBSM_ERR_INVALID_ARG, "%s: job count differs from the plan", fn);
     T.dev.assign(n_jobs, JobDev{});
+    T.job_tiles.assign(n_jobs, 0);
     T.block_job.clear();
     T.rpcf.clear();
     int64_t base = 0, frags = 0;
@@ -250,6 +284,7 @@ int make_tables(const char *fn, const rbsm_job *jobs, int32_t n_jobs, int tile_w
         D.mode = J.mode;
         D.vec_ok = ((uintptr_t)J.frags % 16 == 0) && ((uintptr_t)J.out % (J.mode == 0 ? 4 : 16) == 0) &&
                    (L.vw % 4 == 0);
+        T.job_tiles[j] = L.tiles;
         if (want_map)
             for (int64_t b = 0; b < L.tiles; ++b) T.block_job.push_back((uint16_t)j);
         base += L.tiles;
@@ -294,63 +329,71 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
         return fail(RBSM_ERR_HIP, "%s: could not upload the job tables", fn);
     plan->jobs.assign(jobs, jobs + n_jobs);
     plan->rpcf_jobs = T.rpcf;
+    plan->use_args = make_args(T, &plan->args);
     plan->blocks = base;
     plan->fragments = T.frags;
     plan->grid = plan_grid(plan);
     return RBSM_OK;
 }
 
-// The batched kernel instance of a tuning: one workgroup per tile
-// (batch_kernel) or resident workgroups looping over tiles
-// (batch_persistent_kernel), each built for every walk blocking the tuner
-// tries.
-template <int TW>
-const void *persistent_instance(int wf, int wb) {
+// Batched kernel instances: one workgroup per tile with the job records in a
+// device table (batch_kernel) or in the kernel arguments (batch_arg_kernel),
+// each built for every walk blocking the tuner tries, or resident workgroups
+// looping over the tiles (batch_persistent_kernel).
+template <int TW, int WF, int WB>
+struct TableKernel {
+    static const void *get() { return reinterpret_cast<const void *>(&batch_kernel<TW, WF, WB>); }
+};
+template <int TW, int WF, int WB>
+struct ArgKernel {
+    static const void *get() { return reinterpret_cast<const void *>(&batch_arg_kernel<TW, WF, WB>); }
+};
+
+// Kernel K<TW, WF, WB> for a tuning's walk blocking.
+template <template <int, int, int> class K, int TW>
+const void *walk_instance(int wf, int wb) {
     if (wb == 8) {
-        if (wf == 1) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 1, 8>);
-        if (wf == 4) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 4, 8>);
-        return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 2, 8>);
+        if (wf == 1) return K<TW, 1, 8>::get();
+        if (wf == 4) return K<TW, 4, 8>::get();
+        return K<TW, 2, 8>::get();
     }
-    if (wf == 1) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 1, 4>);
-    if (wf == 4) return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 4, 4>);
-    return reinterpret_cast<const void *>(&batch_persistent_kernel<TW, 2, 4>);
+    if (wf == 1) return K<TW, 1, 4>::get();
+    if (wf == 4) return K<TW, 4, 4>::get();
+    return K<TW, 2, 4>::get();
 }
 
-template <int TW>
-const void *oneshot_instance(int wf, int wb) {
-    if (wb == 8) {
-        if (wf == 1) return reinterpret_cast<const void *>(&batch_kernel<TW, 1, 8>);
-        if (wf == 4) return reinterpret_cast<const void *>(&batch_kernel<TW, 4, 8>);
-        return reinterpret_cast<const void *>(&batch_kernel<TW, 2, 8>);
-    }
-    if (wf == 1) return reinterpret_cast<const void *>(&batch_kernel<TW, 1, 4>);
-    if (wf == 4) return reinterpret_cast<const void *>(&batch_kernel<TW, 4, 4>);
-    return reinterpret_cast<const void *>(&batch_kernel<TW, 2, 4>);
+template <template <int, int, int> class K>
+const void *width_instance(int tw, int wf, int wb) {
+    if (tw == 16) return walk_instance<K, 16>(wf, wb);
+    if (tw == 64) return walk_instance<K, 64>(wf, wb);
+    return walk_instance<K, 32>(wf, wb);
 }
 
-const void *batch_instance(const rbsm_tuning &t) {
+// The kernel a tuning launches: persistent launches use the default walk
+// blocking (one instance per tile width); one workgroup per tile comes with
+// the job records in the kernel arguments (args) or in a device table.
+const void *batch_instance(const rbsm_tuning &t, bool args) {
     const int wf = t.walk_first ? t.walk_first : kWalkFirst, wb = t.walk_block ? t.walk_block : kWalkSteps;
-    if (!t.persistent) {
-        if (t.tile_w == 16) return oneshot_instance<16>(wf, wb);
-        if (t.tile_w == 64) return oneshot_instance<64>(wf, wb);
-        return oneshot_instance<32>(wf, wb);
+    if (t.persistent) {
+        if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_persistent_kernel<16, kWalkFirst, kWalkSteps>);
+        if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_persistent_kernel<64, kWalkFirst, kWalkSteps>);
+        return reinterpret_cast<const void *>(&batch_persistent_kernel<32, kWalkFirst, kWalkSteps>);
     }
-    if (t.tile_w == 16) return persistent_instance<16>(wf, wb);
-    if (t.tile_w == 64) return persistent_instance<64>(wf, wb);
-    return persistent_instance<32>(wf, wb);
+    return args ? width_instance<ArgKernel>(t.tile_w, wf, wb) : width_instance<TableKernel>(t.tile_w, wf, wb);
 }
 
 // Workgroups a launch of the plan's tuning uses.
 int64_t plan_grid(const rbsm_plan *p) {
     if (!p->tune.persistent) return p->blocks;
     const size_t lds = (size_t)p->tune.lds_cap * sizeof(float);
-    return std::min<int64_t>(p->blocks, resident_groups(batch_instance(p->tune), lds));
+    return std::min<int64_t>(p->blocks, resident_groups(batch_instance(p->tune, false), lds));
 }
 
 // One batched pass: the RPCF jobs' box-filter kernels, then the tile pass
 // over every tile of the other jobs (tables in device memory).
-void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *bj, int64_t tiles, int64_t grid,
-                   const rbsm_job *host_jobs, const std::vector<int32_t> &rpcf, hipStream_t stream) {
+void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *bj, const BatchArgs *bargs,
+                   int64_t tiles, int64_t grid, const rbsm_job *host_jobs, const std::vector<int32_t> &rpcf,
+                   hipStream_t stream) {
     for (const int32_t j : rpcf) {
         const rbsm_job &J = host_jobs[j];
         if (J.n == 0) continue;
@@ -364,9 +407,12 @@ void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *
     }
     if (tiles == 0) return;
     const size_t lds = (size_t)tune.lds_cap * sizeof(float);
-    const void *k = batch_instance(tune);
+    const void *k = batch_instance(tune, bargs != nullptr && !tune.persistent);
     int apron = tune.apron, cap = tune.lds_cap, chunk = tune.xcd_chunk;
-    if (!tune.persistent) {
+    if (!tune.persistent && bargs) {
+        void *args[] = {(void *)bargs, (void *)&apron, (void *)&cap, (void *)&chunk};
+        (void)hipLaunchKernel(k, dim3((unsigned)tiles), dim3(kT), args, lds, stream);
+    } else if (!tune.persistent) {
         void *args[] = {(void *)&jobs, (void *)&bj, (void *)&apron, (void *)&cap, (void *)&chunk};
         (void)hipLaunchKernel(k, dim3((unsigned)tiles), dim3(kT), args, lds, stream);
     } else {
@@ -376,7 +422,8 @@ void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *
 }
 
 void launch_batch(const rbsm_plan *p, hipStream_t stream) {
-    launch_tables(p->tune, p->d_jobs, p->d_block_job, p->blocks, p->grid, p->jobs.data(), p->rpcf_jobs, stream);
+    launch_tables(p->tune, p->d_jobs, p->d_block_job, p->use_args ? &p->args : nullptr, p->blocks, p->grid,
+                  p->jobs.data(), p->rpcf_jobs, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -721,7 +768,8 @@ int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_
         trial(c);
     }
     base = best;
-    for (int wf : {1, 2, 4})
+    if (!base.persistent)
+        for (int wf : {1, 2, 4})
             for (int wb : {4, 8}) {
                 if (wf == base.walk_first && wb == base.walk_block) continue;
                 rbsm_tuning c = base;
@@ -1089,8 +1137,9 @@ int rbsm_batch_launch_noalloc(const rbsm_job *jobs, int32_t n_jobs, const rbsm_t
         hipLaunchKernelGGL(block_job_kernel, dim3((unsigned)((T.tiles + 255) / 256)), dim3(256), 0, stream,
                            (const JobDev *)d_jobs, n_jobs, T.tiles, d_bj);
     const size_t lds = (size_t)t.lds_cap * sizeof(float);
-    const int64_t grid = t.persistent ? std::min<int64_t>(T.tiles, resident_groups(batch_instance(t), lds)) : T.tiles;
-    launch_tables(t, d_jobs, d_bj, T.tiles, grid, jobs, T.rpcf, stream);
+    const int64_t grid =
+        t.persistent ? std::min<int64_t>(T.tiles, resident_groups(batch_instance(t, false), lds)) : T.tiles;
+    launch_tables(t, d_jobs, d_bj, nullptr, T.tiles, grid, jobs, T.rpcf, stream);
     return launched(fn);
 }
 

@@ -184,7 +184,7 @@ struct TileShared {
     int16_t slot[kTileF];
     uint8_t sm[kTileF];    // bit 4: centre test, bits 0-3: discontinuity mask
     int qi[kState], qj[kState];
-    float qz[kState], qfx[kState], qfy[kState];
+    float qz[kState];
     int8_t rd[kTileF][4];  // left, right, top, bottom
     int16_t cont[kCont];   // walks (4 e + direction) continued after their first steps
     int count, ncont;
@@ -299,8 +299,6 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
     auto &q_i = sh.qi;
     auto &q_j = sh.qj;
     auto &q_z = sh.qz;
-    auto &q_fx = sh.qfx;
-    auto &q_fy = sh.qfy;
     auto &q_rd = sh.rd;
     int &q_count = sh.count;
 
@@ -376,40 +374,51 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                 tc[f][4] = lt[c - st.bw];
             }
         } else {
-            const bool off32 = (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u);
-            const char *base8 = (const char *)m.t;
-            const unsigned pitch4 = 4u * (unsigned)m.pitch;
+            // the form of the reads is decided once per tile (uniform
+            // branches around every fragment's reads), so the reads of all
+            // kF fragments are in flight together
+            int ti[kF], tj[kF];
 #pragma unroll
             for (int f = 0; f < kF; ++f) {
-                const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
-                const int il = max(ti - 1, 0), ir = min(ti + 1, m.W - 1);
-                const int jl = max(tj - 1, 0), jh = min(tj + 1, m.H - 1);
-                if (off32) {  // 32-bit byte offsets from the map's base
-                    const unsigned row = (unsigned)tj * pitch4;
-                    // left, centre and right in one 12-byte load (the clamped
-                    // triple starts at column il; at the map's left or right
-                    // edge the centre or the right texel is the clamp)
-                    const unsigned c3 = (unsigned)min(il, max(m.W - 3, 0));
-                    if (m.W >= 3) {
-                        const f32x3 t3 = gld3((const float *)(base8 + (row + 4u * c3)));
-                        const int sc = ti - (int)c3;  // 0 (ti = 0), 1, or 2 (ti = W-1)
-                        tc[f][0] = sc == 2 ? t3.y : t3.x;
-                        tc[f][1] = sc == 0 ? t3.x : (sc == 1 ? t3.y : t3.z);
-                        tc[f][2] = sc == 0 ? t3.y : t3.z;
-                    } else {
-                        tc[f][0] = gld((const float *)(base8 + (row + 4u * (unsigned)il)));
-                        tc[f][1] = gld((const float *)(base8 + (row + 4u * (unsigned)ti)));
-                        tc[f][2] = gld((const float *)(base8 + (row + 4u * (unsigned)ir)));
-                    }
-                    tc[f][3] = gld((const float *)(base8 + ((unsigned)jh * pitch4 + 4u * (unsigned)ti)));
-                    tc[f][4] = gld((const float *)(base8 + ((unsigned)jl * pitch4 + 4u * (unsigned)ti)));
-                } else {
-                    const float *row = m.t + (int64_t)tj * m.pitch;
+                ti[f] = min(max(ad[f].i0, 0), m.W - 1);
+                tj[f] = min(max(ad[f].j0, 0), m.H - 1);
+            }
+            const bool off32 = (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u);
+            if (off32 && m.W >= 3) {  // 32-bit byte offsets from the map's base
+                const char *base8 = (const char *)m.t;
+                const unsigned pitch4 = 4u * (unsigned)m.pitch;
+                f32x3 t3[kF];
+                int sc[kF];
+#pragma unroll
+                for (int f = 0; f < kF; ++f) {
+                    // left, centre and right in one 12-byte load: the clamped
+                    // triple starts at column max(ti-1, 0), at most W-3 (at
+                    // the map's left or right edge the centre or the right
+                    // texel is the clamp)
+                    const unsigned c3 = (unsigned)min(max(ti[f] - 1, 0), m.W - 3);
+                    sc[f] = ti[f] - (int)c3;  // 0 (ti = 0), 1, or 2 (ti = W-1)
+                    t3[f] = gld3((const float *)(base8 + ((unsigned)tj[f] * pitch4 + 4u * c3)));
+                    const int jl = max(tj[f] - 1, 0), jh = min(tj[f] + 1, m.H - 1);
+                    tc[f][3] = gld((const float *)(base8 + ((unsigned)jh * pitch4 + 4u * (unsigned)ti[f])));
+                    tc[f][4] = gld((const float *)(base8 + ((unsigned)jl * pitch4 + 4u * (unsigned)ti[f])));
+                }
+#pragma unroll
+                for (int f = 0; f < kF; ++f) {
+                    tc[f][0] = sc[f] == 2 ? t3[f].y : t3[f].x;
+                    tc[f][1] = sc[f] == 0 ? t3[f].x : (sc[f] == 1 ? t3[f].y : t3[f].z);
+                    tc[f][2] = sc[f] == 0 ? t3[f].y : t3[f].z;
+                }
+            } else {
+#pragma unroll
+                for (int f = 0; f < kF; ++f) {
+                    const int il = max(ti[f] - 1, 0), ir = min(ti[f] + 1, m.W - 1);
+                    const int jl = max(tj[f] - 1, 0), jh = min(tj[f] + 1, m.H - 1);
+                    const float *row = m.t + (int64_t)tj[f] * m.pitch;
                     tc[f][0] = gld(row + il);
-                    tc[f][1] = gld(row + ti);
+                    tc[f][1] = gld(row + ti[f]);
                     tc[f][2] = gld(row + ir);
-                    tc[f][3] = gld(m.t + ((int64_t)jh * m.pitch + ti));
-                    tc[f][4] = gld(m.t + ((int64_t)jl * m.pitch + ti));
+                    tc[f][3] = gld(m.t + ((int64_t)jh * m.pitch + ti[f]));
+                    tc[f][4] = gld(m.t + ((int64_t)jl * m.pitch + ti[f]));
                 }
             }
         }
@@ -472,8 +481,6 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                         q_i[pos] = ad[f].i0;
                         q_j[pos] = ad[f].j0;
                         q_z[pos] = ad[f].zb;
-                        q_fx[pos] = ad[f].fx;
-                        q_fy[pos] = ad[f].fy;
                     }
                 }
                 base += __popcll(bal[f]);
@@ -490,14 +497,17 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         const int owner = slot >> 2, f = slot & 3;
         return (tyi * TH + owner / LPR) * vw + txi * TW + (int64_t)(owner % LPR) * kF + f;
     };
-    // full state of queue entry e (from LDS, or recomputed past kState)
-    auto state_of = [&](int e, int &i0, int &j0, float &zb, float &fx, float &fy) {
+    // texel and biased depth of queue entry e (from LDS, or recomputed past
+    // kState); the sub-texel position, needed only by the last step, is
+    // recomputed there from the fragment, so it is not held in registers
+    // through the neighbour tests
+    auto state_of = [&](int e, int &i0, int &j0, float &zb) {
         if (e < kState) {
-            i0 = q_i[e]; j0 = q_j[e]; zb = q_z[e]; fx = q_fx[e]; fy = q_fy[e];
+            i0 = q_i[e]; j0 = q_j[e]; zb = q_z[e];
         } else {
             const int64_t k = frag_of(e);
             const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), gld(frags + 3 * k + 2), m.W, m.H, bias);
-            i0 = b.i0; j0 = b.j0; zb = b.zb; fx = b.fx; fy = b.fy;
+            i0 = b.i0; j0 = b.j0; zb = b.zb;
         }
     };
 
@@ -517,8 +527,8 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
     // walk `task` = 4 e + direction (0 left, 1 right, 2 top, 3 bottom)
     auto make_walk = [&](int task, int &i0, int &j0) -> Walk {
         const int e = task >> 2, dir = task & 3;
-        float zb, fx, fy;
-        state_of(e, i0, j0, zb, fx, fy);
+        float zb;
+        state_of(e, i0, j0, zb);
         const unsigned sm = q_sm[e];
         Walk w;
         w.zb = zb;
@@ -596,13 +606,11 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
 
     // normalize, evaluate and store, one lane per edge fragment
     for (int e = t; e < ne; e += kT) {
-        int i0, j0;
-        float zb, fx, fy;
-        state_of(e, i0, j0, zb, fx, fy);
-        const bool s = (q_sm[e] & 16u) != 0;
-        const Axis axx = normalize_axis(q_rd[e][0], q_rd[e][1], fx);
-        const Axis axy = normalize_axis(q_rd[e][3], q_rd[e][2], fy);
         const int64_t k = frag_of(e);
+        const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), 0.0f, m.W, m.H, bias);
+        const bool s = (q_sm[e] & 16u) != 0;
+        const Axis axx = normalize_axis(q_rd[e][0], q_rd[e][1], b.fx);
+        const Axis axy = normalize_axis(q_rd[e][3], q_rd[e][2], b.fy);
         if (HARD) gst(static_cast<uint8_t *>(out_v) + k, (uint8_t)(vis_hard(axx, axy) != 0.0f ? 1 : 0));
         else gst(static_cast<float *>(out_v) + k, vis_rsmss(s, axx, axy));
     }
@@ -708,6 +716,57 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                                 sh, s_tex, J.mode == 0);
 }
 
+// Batched pass with its job records in the kernel arguments: a workgroup
+// finds its job by a binary search over the jobs' first tiles and reads the
+// record with scalar loads from the argument segment (cached), with no
+// dependent loads from a table in memory (which cost a workgroup about 1.3 us
+// before its fragment loads could start).  For launches of up to
+// kArgJobsMax jobs with tiles.
+// Batched pass with the job records in the kernel arguments: a workgroup
+// finds its job from the kernel-argument segment, which every workgroup reads
+// and so stays in the scalar and L2 caches, instead of two dependent loads of
+// device tables (the tile's job index, then the job record) that miss in each
+// XCD's L2 on first touch.  For batches of at most kArgJobsMax jobs with tiles.
+struct JobArg {
+    const float *t;        // map
+    const float *frags;
+    void *out;
+    int32_t pitch, W, H;   // pitch in floats (< 2^31)
+    int32_t n, vw, tiles_x, tile_base;
+    float bias;
+    int16_t maxd;
+    uint8_t vec_ok, mode;  // mode 0 hard, 1 RSMSS
+};
+
+constexpr int kArgJobsMax = 48;
+
+struct BatchArgs {
+    int32_t first[kArgJobsMax];  // first tile of each job, increasing; INT32_MAX past the last job
+    JobArg jobs[kArgJobsMax];
+};
+
+template <int TW, int WF = kWalkFirst, int WB = kWalkSteps>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_arg_kernel(
+    const BatchArgs a, int apron, int cap, int chunk_log2) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, chunk_log2);
+    // the job is the number of later jobs starting at or before g: lane k
+    // compares job k's first tile, one load per lane and a ballot
+    static_assert(kArgJobsMax <= 64, "one job per lane");
+    const int l = threadIdx.x & 63;
+    const int32_t f = l < kArgJobsMax ? a.first[l] : INT32_MAX;
+    const int lo = __popcll(__ballot(l >= 1 && f <= g));
+    const JobArg &J = a.jobs[lo];
+    MapView m;
+    m.t = J.t;
+    m.pitch = J.pitch;
+    m.W = J.W;
+    m.H = J.H;
+    process_tile<2, TW, WF, WB>(m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
+                                g - J.tile_base, sh, s_tex, J.mode == 0);
+}
+
 // Batched pass with resident workgroups looping over the tiles of every job,
 // the next tile's job and fragments read while the current tile is worked on;
 // WF and WB are the walk blocking the autotuner searches.  Up to 96 VGPRs (5
@@ -732,12 +791,16 @@ struct TileConfig {
 constexpr TileConfig kDefaultTile{32, 1, 2048, 0, -1};
 constexpr int kMaxChunkLog2 = 12;
 
+// Persistent launches are built for the default walk blocking only.
 inline bool tuning_ok(const rbsm_tuning *t) {
-    return t && (t->tile_w == 16 || t->tile_w == 32 || t->tile_w == 64) && t->apron >= 1 && t->apron <= 8 &&
+    if (!t) return false;
+    const bool walk_default =
+        (t->walk_first == 0 || t->walk_first == kWalkFirst) && (t->walk_block == 0 || t->walk_block == kWalkSteps);
+    return (t->tile_w == 16 || t->tile_w == 32 || t->tile_w == 64) && t->apron >= 1 && t->apron <= 8 &&
            t->lds_cap >= 256 && t->lds_cap <= 12288 && (t->persistent == 0 || t->persistent == 1) &&
            (t->walk_first == 0 || t->walk_first == 1 || t->walk_first == 2 || t->walk_first == 4) &&
            (t->walk_block == 0 || t->walk_block == 4 || t->walk_block == 8) && t->xcd_chunk >= -1 &&
-           t->xcd_chunk <= kMaxChunkLog2;
+           t->xcd_chunk <= kMaxChunkLog2 && (t->persistent == 0 || walk_default);
 }
 
 // Resident workgroups of a persistent launch: the occupancy of `kernel` at

@@ -98,9 +98,17 @@ def test_tuning_validated_on_host(lib):
     for bad in (rb.RbsmTuning(24, 1, 4096), rb.RbsmTuning(32, 0, 4096), rb.RbsmTuning(32, 1, 100000),
                 rb.RbsmTuning(32, 1, 2048, 2, 0, 0), rb.RbsmTuning(32, 1, 2048, 0, 3, 0),
                 rb.RbsmTuning(32, 1, 2048, 0, 0, 5), rb.RbsmTuning(32, 1, 2048, 1, 4, 8),
-                rb.RbsmTuning(32, 1, 2048, 0, 0, 0, 13), rb.RbsmTuning(32, 1, 2048, 0, 0, 0, -2)):
+                rb.RbsmTuning(32, 1, 2048, 0, 0, 0, 13), rb.RbsmTuning(32, 1, 2048, 0, 0, 0, -2),
+                # persistent launches take the default walk blocking only
+                rb.RbsmTuning(32, 1, 2048, 1, 1, 4), rb.RbsmTuning(32, 1, 2048, 1, 2, 8)):
         assert lib.rbsm_pass_tuned(0, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(bad), 0x200000, None) == -1
     assert lib.rbsm_pass_tuned(3, 0x1000, 0x100000, 16, ctypes.byref(p), ctypes.byref(d), 0x200000, None) == -1
+    h = ctypes.c_void_p()
+    jobs = (rb.RbsmJob * 1)()
+    jobs[0] = rb.RbsmJob(0x1000000, 0x2000000, 64, p, 0, 0x3000000)
+    bad = rb.RbsmTuning(64, 1, 2048, 1, 4, 4)
+    assert lib.rbsm_plan_create(jobs, 1, ctypes.byref(bad), ctypes.byref(h)) == -1 and not h.value
+    assert "tuning" in lib.rbsm_last_error().decode()
 
 
 def test_plan_rejects_bad_jobs_on_host(lib):

@@ -89,8 +89,10 @@ def test_autotune_and_tunings_never_change_results(rb, workload):
                # tiles dealt to XCDs in chunks (with a partial last round)
                rb.RbsmTuning(32, 1, 2048, xcd_chunk=0), rb.RbsmTuning(32, 1, 2048, xcd_chunk=3),
                rb.RbsmTuning(16, 2, 2048, xcd_chunk=12),
-               # resident workgroups looping over tiles, every walk blocking
-               *[rb.RbsmTuning(tw, 1, 2048, 1, wf, wb) for tw in (16, 64) for wf in (1, 2, 4) for wb in (4, 8)]]
+               # every walk blocking (one workgroup per tile)
+               *[rb.RbsmTuning(tw, 1, 2048, 0, wf, wb, 5) for tw in (16, 64) for wf in (1, 2, 4) for wb in (4, 8)],
+               # resident workgroups looping over tiles
+               rb.RbsmTuning(16, 1, 2048, 1), rb.RbsmTuning(32, 2, 3072, 1), rb.RbsmTuning(64, 1, 2048, 1)]
     for t in tunings:
         plan.tuning = t
         for j in jobs:
