@@ -133,7 +133,8 @@ typedef struct {
     int32_t tile_w;     /* screen-tile width in pixels: 16, 32 or 64 (height 1024 / tile_w);
                            ignored (flat 1024-fragment chunks) when view_width is 0 */
     int32_t apron;      /* texels staged around the tile's texel box, 1..8 */
-    int32_t lds_cap;    /* LDS texel capacity per workgroup, 256..12288 */
+    int32_t lds_cap;    /* LDS texel capacity per workgroup, 256..12288, or 0:
+                           nothing staged, every texel read from global memory */
     int32_t persistent; /* 0: one workgroup per screen tile; 1: only resident
                            workgroups, each looping over tiles and loading the
                            next tile's fragments while it works on the current one */

@@ -369,11 +369,16 @@ const void *width_instance(int tw, int wf, int wb) {
     return walk_instance<K, 32>(wf, wb);
 }
 
-// The kernel a tuning launches: persistent launches use the default walk
-// blocking (one instance per tile width); one workgroup per tile comes with
-// the job records in the kernel arguments (args) or in a device table.
+// The kernel a tuning launches, with the job records in the kernel arguments
+// (args) or in device tables: persistent launches use the default walk
+// blocking (one instance per tile width).
 const void *batch_instance(const rbsm_tuning &t, bool args) {
     const int wf = t.walk_first ? t.walk_first : kWalkFirst, wb = t.walk_block ? t.walk_block : kWalkSteps;
+    if (t.persistent && args) {
+        if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_arg_loop_kernel<16>);
+        if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_arg_loop_kernel<64>);
+        return reinterpret_cast<const void *>(&batch_arg_loop_kernel<32>);
+    }
     if (t.persistent) {
         if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_persistent_kernel<16, kWalkFirst, kWalkSteps>);
         if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_persistent_kernel<64, kWalkFirst, kWalkSteps>);
@@ -386,7 +391,7 @@ const void *batch_instance(const rbsm_tuning &t, bool args) {
 int64_t plan_grid(const rbsm_plan *p) {
     if (!p->tune.persistent) return p->blocks;
     const size_t lds = (size_t)p->tune.lds_cap * sizeof(float);
-    return std::min<int64_t>(p->blocks, resident_groups(batch_instance(p->tune, false), lds));
+    return std::min<int64_t>(p->blocks, resident_groups(batch_instance(p->tune, p->use_args), lds));
 }
 
 // One batched pass: the RPCF jobs' box-filter kernels, then the tile pass
@@ -407,9 +412,13 @@ void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *
     }
     if (tiles == 0) return;
     const size_t lds = (size_t)tune.lds_cap * sizeof(float);
-    const void *k = batch_instance(tune, bargs != nullptr && !tune.persistent);
+    const void *k = batch_instance(tune, bargs != nullptr);
     int apron = tune.apron, cap = tune.lds_cap, chunk = tune.xcd_chunk;
-    if (!tune.persistent && bargs) {
+    if (tune.persistent && bargs) {
+        int n_tiles = (int)tiles;  // below 2^24
+        void *args[] = {(void *)bargs, (void *)&n_tiles, (void *)&apron, (void *)&cap, (void *)&chunk};
+        (void)hipLaunchKernel(k, dim3((unsigned)grid), dim3(kT), args, lds, stream);
+    } else if (!tune.persistent && bargs) {
         void *args[] = {(void *)bargs, (void *)&apron, (void *)&cap, (void *)&chunk};
         (void)hipLaunchKernel(k, dim3((unsigned)tiles), dim3(kT), args, lds, stream);
     } else if (!tune.persistent) {
@@ -749,20 +758,20 @@ int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_
             trial(c);
         }
     base = best;
-    if (!base.persistent)
+    if (!base.persistent || plan->use_args)  // the table-driven persistent loop has its own order
         for (int chunk : {3, 5, 7}) {
             rbsm_tuning c = base;
             c.xcd_chunk = chunk;
             trial(c);
         }
     base = best;
-    for (int cap : {1536, 3072, 4096}) {
+    for (int cap : {0, 1536, 3072, 4096}) {
         rbsm_tuning c = base;
         c.lds_cap = cap;
         trial(c);
     }
     base = best;
-    {
+    if (base.lds_cap != 0) {  // the apron matters only where tiles are staged
         rbsm_tuning c = base;
         c.apron = base.apron == 1 ? 2 : 1;
         trial(c);

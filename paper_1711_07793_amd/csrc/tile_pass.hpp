@@ -77,35 +77,51 @@ constexpr int kStageChunk = 8;  // texels per thread whose loads are in flight t
 // (+-1, +-w) with clamp-to-edge already applied.  Each thread issues
 // kStageChunk loads before its first LDS store, so a chunk costs one memory
 // round trip.
-//  - a window inside a map under 4 GiB and at most kT texels wide: every
-//    thread owns one column and kT / w rows per round; a texel costs a
-//    32-bit address add, a row compare and an LDS address add;
+//  - a window at most kT texels wide in a map under 4 GiB: every thread owns
+//    one column (its clamped x fixed) and kT / w rows per round; a texel costs
+//    a 32-bit address add (a row clamp where the window leaves the map), a
+//    row compare and an LDS address add;
 //  - otherwise the threads stride over the window with clamped coordinates.
 __device__ __forceinline__ void stage_rect(const MapView &m, float *dst, int x0, int y0, int w, int h, int t) {
-    const bool inside = x0 >= 0 && y0 >= 0 && x0 + w <= m.W && y0 + h <= m.H;
-    if (inside && w <= kT && (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u)) {
+    if (w <= kT && (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u)) {
         const int rpi = kT / w;  // rows per round
         const int c = t % w, r0 = t / w;
         if (r0 >= rpi) return;   // the kT % w threads without a column
         const char *base8 = (const char *)m.t;
         const unsigned pitch4 = 4u * (unsigned)m.pitch;
-        const unsigned dstep = (unsigned)rpi * pitch4;
+        const unsigned x4 = 4u * (unsigned)min(max(x0 + c, 0), m.W - 1);
         const int lstep = rpi * w;
-        unsigned off = (unsigned)(y0 + r0) * pitch4 + 4u * (unsigned)(x0 + c);
         int li = r0 * w + c;
-        for (int r = r0; r < h; r += rpi * kStageChunk) {
-            float v[kStageChunk];
+        if (y0 >= 0 && y0 + h <= m.H) {  // rows inside the map: no row clamp
+            const unsigned dstep = (unsigned)rpi * pitch4;
+            unsigned off = (unsigned)(y0 + r0) * pitch4 + x4;
+            for (int r = r0; r < h; r += rpi * kStageChunk) {
+                float v[kStageChunk];
 #pragma unroll
-            for (int u = 0; u < kStageChunk; ++u) {
-                // rows past the window re-read the first row (in bounds) and are not stored
-                const bool ok = r + u * rpi < h;
-                v[u] = gld((const float *)(base8 + (ok ? off + (unsigned)u * dstep : off)));
+                for (int u = 0; u < kStageChunk; ++u) {
+                    // rows past the window re-read the first row (in bounds) and are not stored
+                    const bool ok = r + u * rpi < h;
+                    v[u] = gld((const float *)(base8 + (ok ? off + (unsigned)u * dstep : off)));
+                }
+#pragma unroll
+                for (int u = 0; u < kStageChunk; ++u)
+                    if (r + u * rpi < h) dst[li + u * lstep] = v[u];
+                off += (unsigned)kStageChunk * dstep;
+                li += kStageChunk * lstep;
             }
+        } else {
+            for (int r = r0; r < h; r += rpi * kStageChunk) {
+                float v[kStageChunk];
 #pragma unroll
-            for (int u = 0; u < kStageChunk; ++u)
-                if (r + u * rpi < h) dst[li + u * lstep] = v[u];
-            off += (unsigned)kStageChunk * dstep;
-            li += kStageChunk * lstep;
+                for (int u = 0; u < kStageChunk; ++u) {
+                    const int y = min(max(y0 + r + u * rpi, 0), m.H - 1);  // rows past the window: clamped, not stored
+                    v[u] = gld((const float *)(base8 + ((unsigned)y * pitch4 + x4)));
+                }
+#pragma unroll
+                for (int u = 0; u < kStageChunk; ++u)
+                    if (r + u * rpi < h) dst[li + u * lstep] = v[u];
+                li += kStageChunk * lstep;
+            }
         }
         return;
     }
@@ -184,7 +200,7 @@ struct TileShared {
     int16_t slot[kTileF];
     uint8_t sm[kTileF];    // bit 4: centre test, bits 0-3: discontinuity mask
     int qi[kState], qj[kState];
-    float qz[kState];
+    float qz[kState], qfx[kState], qfy[kState];  // sub-texel position: written by the walk phase
     int8_t rd[kTileF][4];  // left, right, top, bottom
     int16_t cont[kCont];   // walks (4 e + direction) continued after their first steps
     int count, ncont;
@@ -306,7 +322,7 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
     const int lane = t & 63, wave = t >> 6;
     const TilePos<TW> P(vw, n, tiles_x, tile_id, t);
     const int64_t tyi = P.tyi, txi = P.txi, k0 = P.k0;
-    const unsigned long long below = __lanemask_lt();
+    const unsigned long long below = (1ull << lane) - 1ull;  // lanes below this one (from the opaque index)
 
     Staged st;
     {
@@ -315,45 +331,72 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         for (int f = 0; f < kF; ++f) valid[f] = f < P.avail;
         const bool full = vec_ok && valid[kF - 1];
 
-        Addr ad[kF];
-        // clamped texel indices lie in [0, 65535]: -1 marks "no fragment"
-        int imin = INT32_MAX, imax = -1, jmin = INT32_MAX, jmax = -1;
-#pragma unroll
-        for (int f = 0; f < kF; ++f) {
-            ad[f] = address(fr[3 * f], fr[3 * f + 1], fr[3 * f + 2], m.W, m.H, bias);
-            if (valid[f]) {
-                const int ic = min(max(ad[f].i0, 0), m.W - 1), jc = min(max(ad[f].j0, 0), m.H - 1);
-                imin = min(imin, ic); imax = max(imax, ic);
-                jmin = min(jmin, jc); jmax = max(jmax, jc);
+        // cap == 0: direct reads, no box and no staging.  The queue counters
+        // are cleared before the first fragment value is used, so the
+        // barrier overlaps the fragment loads.
+        const bool direct = cap == 0;
+        auto clear_queue = [&] {
+            if (t == 0) {
+                // t - t: zero made from the thread index, so a loop over tiles
+                // does not hold a zero pair in registers across tiles
+                const int zero = t - opaque_tid();
+                q_count = zero;
+                sh.ncont = zero;
             }
+        };
+        if (direct) {
+            clear_queue();
+            __syncthreads();
         }
-        imin = wave_min(imin);
-        imax = -wave_min(-imax);
-        jmin = wave_min(jmin);
-        jmax = -wave_min(-jmax);
-        if (lane == 0) {
-            s_box[wave][0] = imin; s_box[wave][1] = imax;
-            s_box[wave][2] = jmin; s_box[wave][3] = jmax;
-        }
-        if (t == 0) {
-            q_count = 0;
-            sh.ncont = 0;
-        }
-        __syncthreads();
-        prefetch();
+        Addr ad[kF];
 #pragma unroll
-        for (int w = 0; w < kT / 64; ++w) {
-            imin = min(imin, s_box[w][0]); imax = max(imax, s_box[w][1]);
-            jmin = min(jmin, s_box[w][2]); jmax = max(jmax, s_box[w][3]);
-        }
+        for (int f = 0; f < kF; ++f) ad[f] = address(fr[3 * f], fr[3 * f + 1], fr[3 * f + 2], m.W, m.H, bias);
         st.lds = s_tex;
-        st.bx0 = imin - apron;
-        st.by0 = jmin - apron;
-        st.bw = imax - imin + 1 + 2 * apron;
-        st.bh = jmax - jmin + 1 + 2 * apron;
-        st.on = imin <= imax && (int64_t)st.bw * st.bh <= (int64_t)cap;
-        if (st.on) stage_rect(m, s_tex, st.bx0, st.by0, st.bw, st.bh, t);
-        __syncthreads();
+        st.on = false;
+        if (direct) {
+            prefetch();
+        } else {
+            // clamped texel indices lie in [0, 65535]: -1 marks "no fragment"
+            int imin = INT32_MAX, imax = -1, jmin = INT32_MAX, jmax = -1;
+#pragma unroll
+            for (int f = 0; f < kF; ++f)
+                if (valid[f]) {
+                    const int ic = min(max(ad[f].i0, 0), m.W - 1), jc = min(max(ad[f].j0, 0), m.H - 1);
+                    imin = min(imin, ic); imax = max(imax, ic);
+                    jmin = min(jmin, jc); jmax = max(jmax, jc);
+                }
+            imin = wave_min(imin);
+            imax = -wave_min(-imax);
+            jmin = wave_min(jmin);
+            jmax = -wave_min(-jmax);
+            if (lane == 0) {
+                s_box[wave][0] = imin; s_box[wave][1] = imax;
+                s_box[wave][2] = jmin; s_box[wave][3] = jmax;
+            }
+            clear_queue();
+            __syncthreads();
+            prefetch();
+#pragma unroll
+            for (int w = 0; w < kT / 64; ++w) {
+                imin = min(imin, s_box[w][0]); imax = max(imax, s_box[w][1]);
+                jmin = min(jmin, s_box[w][2]); jmax = max(jmax, s_box[w][3]);
+            }
+            // the box is the same in every lane: as wave-uniform values the
+            // window and the staged / unstaged choice become scalar code and
+            // uniform branches (the reads of one path then never wait for
+            // reads the other path might have issued)
+            imin = __builtin_amdgcn_readfirstlane(imin);
+            imax = __builtin_amdgcn_readfirstlane(imax);
+            jmin = __builtin_amdgcn_readfirstlane(jmin);
+            jmax = __builtin_amdgcn_readfirstlane(jmax);
+            st.bx0 = imin - apron;
+            st.by0 = jmin - apron;
+            st.bw = imax - imin + 1 + 2 * apron;
+            st.bh = jmax - jmin + 1 + 2 * apron;
+            st.on = imin <= imax && (int64_t)st.bw * st.bh <= (int64_t)cap;
+            if (st.on) stage_rect(m, s_tex, st.bx0, st.by0, st.bw, st.bh, t);
+            __syncthreads();
+        }
 
         // centre and neighbour texels; the staged path reads through an LDS
         // address-space pointer so its loads stay ds_reads (a merged generic
@@ -366,7 +409,8 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
 #pragma unroll
             for (int f = 0; f < kF; ++f) {
                 const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
-                const int c = valid[f] ? (tj - st.by0) * st.bw + (ti - st.bx0) : st.bw + 1;
+                // 24-bit multiply: the row is below the window height and bw below 2^14
+                const int c = valid[f] ? __mul24(tj - st.by0, st.bw) + (ti - st.bx0) : st.bw + 1;
                 tc[f][0] = lt[c - 1];
                 tc[f][1] = lt[c];
                 tc[f][2] = lt[c + 1];
@@ -397,10 +441,11 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                     // texel is the clamp)
                     const unsigned c3 = (unsigned)min(max(ti[f] - 1, 0), m.W - 3);
                     sc[f] = ti[f] - (int)c3;  // 0 (ti = 0), 1, or 2 (ti = W-1)
-                    t3[f] = gld3((const float *)(base8 + ((unsigned)tj[f] * pitch4 + 4u * c3)));
+                    t3[f] = gld3((const float *)(base8 + (__umul24((unsigned)tj[f], pitch4) + 4u * c3)));
                     const int jl = max(tj[f] - 1, 0), jh = min(tj[f] + 1, m.H - 1);
-                    tc[f][3] = gld((const float *)(base8 + ((unsigned)jh * pitch4 + 4u * (unsigned)ti[f])));
-                    tc[f][4] = gld((const float *)(base8 + ((unsigned)jl * pitch4 + 4u * (unsigned)ti[f])));
+                    // 24-bit multiplies: rows below 2^16, pitch4 below 2^18
+                    tc[f][3] = gld((const float *)(base8 + (__umul24((unsigned)jh, pitch4) + 4u * (unsigned)ti[f])));
+                    tc[f][4] = gld((const float *)(base8 + (__umul24((unsigned)jl, pitch4) + 4u * (unsigned)ti[f])));
                 }
 #pragma unroll
                 for (int f = 0; f < kF; ++f) {
@@ -470,7 +515,7 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         if (wave_total) {
             int base = 0;
             if (lane == 0) base = atomicAdd(&q_count, wave_total);
-            base = __shfl(base, 0);
+            base = __builtin_amdgcn_readfirstlane(base);  // every lane is active here: lane 0's value
 #pragma unroll
             for (int f = 0; f < kF; ++f) {
                 const int pos = base + __popcll(bal[f] & below);
@@ -555,16 +600,27 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
     };
     const int first = min(WF, maxd);
     for (int task = t; task < 4 * ne; task += kT) {
+        // the left walk's lane also reads the fragment's (u, v) for the last
+        // step, in the same round trip as its walk's first reads
+        const int e_uv = task >> 2;
+        const bool uv = (task & 3) == 0 && e_uv < kState;
+        float u = 0.0f, v = 0.0f;
+        if (uv) {
+            const int64_t k = frag_of(e_uv);
+            u = gld(frags + 3 * k);
+            v = gld(frags + 3 * k + 1);
+        }
         int i0, j0;
         const Walk w = make_walk(task, i0, j0);
         int rd;
+        bool queued = false;  // continued after the barrier
         if (map_32) {
             rd = walk_range<WF>(w.r, 1, first, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
             if (rd == 0 && first < maxd) {
                 const int slot = atomicAdd(&sh.ncont, 1);
-                if (slot < kCont) sh.cont[slot] = (int16_t)task;  // continued below
+                queued = slot < kCont;
+                if (queued) sh.cont[slot] = (int16_t)task;
                 else rd = walk_range<WB>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
-                if (slot < kCont) continue;
             }
             if (rd == 0) rd = -(maxd + 1);
         } else {
@@ -589,7 +645,12 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                 }
             }
         }
-        q_rd[task >> 2][task & 3] = (int8_t)rd;
+        if (!queued) q_rd[task >> 2][task & 3] = (int8_t)rd;
+        if (uv) {
+            const Addr b = address(u, v, 0.0f, m.W, m.H, bias);
+            sh.qfx[e_uv] = b.fx;
+            sh.qfy[e_uv] = b.fy;
+        }
     }
     __syncthreads();
     const int nc = min(sh.ncont, kCont);
@@ -607,10 +668,18 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
     // normalize, evaluate and store, one lane per edge fragment
     for (int e = t; e < ne; e += kT) {
         const int64_t k = frag_of(e);
-        const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), 0.0f, m.W, m.H, bias);
+        float fx, fy;
+        if (e < kState) {
+            fx = sh.qfx[e];
+            fy = sh.qfy[e];
+        } else {
+            const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), 0.0f, m.W, m.H, bias);
+            fx = b.fx;
+            fy = b.fy;
+        }
         const bool s = (q_sm[e] & 16u) != 0;
-        const Axis axx = normalize_axis(q_rd[e][0], q_rd[e][1], b.fx);
-        const Axis axy = normalize_axis(q_rd[e][3], q_rd[e][2], b.fy);
+        const Axis axx = normalize_axis(q_rd[e][0], q_rd[e][1], fx);
+        const Axis axy = normalize_axis(q_rd[e][3], q_rd[e][2], fy);
         if (HARD) gst(static_cast<uint8_t *>(out_v) + k, (uint8_t)(vis_hard(axx, axy) != 0.0f ? 1 : 0));
         else gst(static_cast<float *>(out_v) + k, vis_rsmss(s, axx, axy));
     }
@@ -745,19 +814,22 @@ struct BatchArgs {
     JobArg jobs[kArgJobsMax];
 };
 
-template <int TW, int WF = kWalkFirst, int WB = kWalkSteps>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_arg_kernel(
-    const BatchArgs a, int apron, int cap, int chunk_log2) {
-    extern __shared__ float s_tex[];
-    __shared__ TileShared sh;
-    const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, chunk_log2);
-    // the job is the number of later jobs starting at or before g: lane k
-    // compares job k's first tile, one load per lane and a ballot
-    static_assert(kArgJobsMax <= 64, "one job per lane");
-    const int l = threadIdx.x & 63;
-    const int32_t f = l < kArgJobsMax ? a.first[l] : INT32_MAX;
-    const int lo = __popcll(__ballot(l >= 1 && f <= g));
-    const JobArg &J = a.jobs[lo];
+// The job of launch tile g: binary search over the first tiles in the
+// argument segment, scalar loads that hit the scalar cache (a launch has fewer
+// than 2^24 tiles; g is wave-uniform).
+__device__ __forceinline__ int arg_job(const BatchArgs &a, int64_t g) {
+    const int g32 = __builtin_amdgcn_readfirstlane((int)g);
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (lo + step < kArgJobsMax && a.first[lo + step] <= g32) lo += step;
+    return lo;
+}
+
+template <int TW, int WF, int WB>
+__device__ __forceinline__ void arg_tile(const BatchArgs &a, int64_t g, int apron, int cap, TileShared &sh,
+                                         float *s_tex) {
+    const JobArg &J = a.jobs[arg_job(a, g)];
     MapView m;
     m.t = J.t;
     m.pitch = J.pitch;
@@ -765,6 +837,30 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     m.H = J.H;
     process_tile<2, TW, WF, WB>(m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
                                 g - J.tile_base, sh, s_tex, J.mode == 0);
+}
+
+template <int TW, int WF = kWalkFirst, int WB = kWalkSteps>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_arg_kernel(
+    const BatchArgs a, int apron, int cap, int chunk_log2) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    arg_tile<TW, WF, WB>(a, xcd_chunked(blockIdx.x, gridDim.x, chunk_log2), apron, cap, sh, s_tex);
+}
+
+// The same pass with resident workgroups (grid G, a multiple of 8) looping
+// over the launch's tiles, so no workgroup waits to be dispatched: workgroup
+// b takes the virtual blocks b, b + G, b + 2G, ... (all on b's XCD) and
+// processes the tiles xcd_chunked deals to them.  Nothing is carried from one
+// tile to the next, so the loop fits the one-shot kernel's 64 VGPRs.
+template <int TW>
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_arg_loop_kernel(
+    const BatchArgs a, int tiles, int apron, int cap, int chunk_log2) {
+    extern __shared__ float s_tex[];
+    __shared__ TileShared sh;
+    for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
+        arg_tile<TW, kWalkFirst, kWalkSteps>(a, xcd_chunked(v, tiles, chunk_log2), apron, cap, sh, s_tex);
+        __syncthreads();  // the next tile reuses the shared state
+    }
 }
 
 // Batched pass with resident workgroups looping over the tiles of every job,
@@ -797,7 +893,8 @@ inline bool tuning_ok(const rbsm_tuning *t) {
     const bool walk_default =
         (t->walk_first == 0 || t->walk_first == kWalkFirst) && (t->walk_block == 0 || t->walk_block == kWalkSteps);
     return (t->tile_w == 16 || t->tile_w == 32 || t->tile_w == 64) && t->apron >= 1 && t->apron <= 8 &&
-           t->lds_cap >= 256 && t->lds_cap <= 12288 && (t->persistent == 0 || t->persistent == 1) &&
+           (t->lds_cap == 0 || (t->lds_cap >= 256 && t->lds_cap <= 12288)) &&
+           (t->persistent == 0 || t->persistent == 1) &&
            (t->walk_first == 0 || t->walk_first == 1 || t->walk_first == 2 || t->walk_first == 4) &&
            (t->walk_block == 0 || t->walk_block == 4 || t->walk_block == 8) && t->xcd_chunk >= -1 &&
            t->xcd_chunk <= kMaxChunkLog2 && (t->persistent == 0 || walk_default);

@@ -86,6 +86,8 @@ def test_autotune_and_tunings_never_change_results(rb, workload):
     torch.cuda.synchronize()
     want = [j["out"].cpu().numpy().copy() for j in jobs]
     tunings = [rb.RbsmTuning(16, 1, 256), rb.RbsmTuning(64, 3, 4096),
+               # direct reads (nothing staged), one workgroup per tile and resident
+               rb.RbsmTuning(32, 1, 0, 0, 0, 0, 5), rb.RbsmTuning(64, 1, 0, 1, 0, 0, 5),
                # tiles dealt to XCDs in chunks (with a partial last round)
                rb.RbsmTuning(32, 1, 2048, xcd_chunk=0), rb.RbsmTuning(32, 1, 2048, xcd_chunk=3),
                rb.RbsmTuning(16, 2, 2048, xcd_chunk=12),

@@ -455,7 +455,7 @@ def test_tiles_too_large_for_lds_read_global(rb):
 
 
 @pytest.mark.parametrize("tw", [16, 32, 64])
-@pytest.mark.parametrize("cap", [256, 2048, 12288])
+@pytest.mark.parametrize("cap", [0, 256, 2048, 12288])  # 0: direct reads, nothing staged
 def test_tuning_never_changes_results(rb, tw, cap):
     c = synth.make_config(2, 2006, small=True)
     md, fd = dev(c["map"]), dev(c["frags"])

@@ -55,7 +55,7 @@ def _noalloc_c_abi(rb, jobs, tuning):
     return [j["out"].cpu().numpy() for j in jobs]
 
 
-@pytest.mark.parametrize("tuning", [None, (64, 1, 2048, 0, 0, 0, 5), (32, 2, 2048, 1, 2, 8, -1)])
+@pytest.mark.parametrize("tuning", [None, (64, 1, 2048, 0, 1, 8, 5), (32, 2, 2048, 1, 0, 0, -1)])
 def test_noalloc_equals_plan_twice_then_smaller(rb, tuning):
     w = synth.make_batched(4001, small=True)
     maps, jobs = _jobs(rb, w, radius=True)
