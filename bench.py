@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "shaded fragments/sec (RBSM, RSMSS) batched vs plain per-view; p99 frame latency"
 PEAK_HBM_GBPS = 8000.0
 ROTATE_BYTES = 512 << 20
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "batch_kernel_16maps_8views_traffic.md")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "batch_arg_kernel_16maps_8views_traffic.md")
 
 
 def kernel_source_hash() -> str:
@@ -49,8 +49,10 @@ def kernel_source_hash() -> str:
 
 def read_traffic(kernel_hash: str, tuning: dict, path: str = PROFILE_TRAFFIC):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source or
-    launch tuning."""
+    None when it is missing, was taken on a different kernel source, or holds
+    no entry for this launch tuning.  The summary ends with lines
+    ``- kernel_source_sha: `<sha>` `` and, per profiled tuning,
+    ``- hbm_bytes_per_launch <tuning label>: `<bytes>` ``."""
     if not os.path.exists(path):
         return None
     vals = {}
@@ -58,10 +60,10 @@ def read_traffic(kernel_hash: str, tuning: dict, path: str = PROFILE_TRAFFIC):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha") != kernel_hash or vals.get("tuning") != tuning_label(tuning):
+    if vals.get("kernel_source_sha") != kernel_hash:
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch " + tuning_label(tuning)])
     except (KeyError, ValueError):
         return None
 
@@ -263,17 +265,23 @@ def frame_rate(torch, frame_fn, sync_fn, n_frag: int, frames: int, warmup: int =
             "p99_frame_ms": float(np.percentile(lat, 99)), "frames": frames}
 
 
-def batched_headline(torch, rb, bf: BatchedFrame, steps: int, warmup: int, latency_frames: int = 200):
+def batched_headline(torch, rb, bf: BatchedFrame, steps: int, warmup: int, latency_frames: int = 200,
+                     fixed_tuning=None):
     """The headline: plain per-view launches of the 48 jobs, then the
-    autotuned batched plan captured as a HIP graph.  Exactly `steps` graph
-    replays run back to back between synchronisations; one HIP event pair on
-    the replay stream brackets them (the kernel's average duration)."""
+    autotuned (or, with fixed_tuning, the given) batched plan captured as a
+    HIP graph.  Exactly `steps` graph replays run back to back between
+    synchronisations; one HIP event pair on the replay stream brackets them
+    (the kernel's average duration)."""
     stream = torch.cuda.current_stream()
     sh = int(stream.cuda_stream)
     plain = frame_rate(torch, lambda: bf.plain_frame(sh), torch.cuda.synchronize, bf.n_frag, 30)
     want = bf.outputs()
     plan = rb.Plan(bf.jobs)
-    tune = plan.autotune(reps=3).as_dict()
+    if fixed_tuning is None:
+        tune = plan.autotune(reps=10).as_dict()
+    else:
+        plan.tuning = fixed_tuning
+        tune = plan.tuning.as_dict()
     for j in bf.jobs:
         j["out"].fill_(0)
     plan.launch()
@@ -751,6 +759,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--tuning", default=None,
+                    help="headline: launch this tuning (tile_w,apron,lds_cap,persistent,walk_first,walk_block,"
+                         "xcd_chunk) instead of autotuning (for counter runs of one launch configuration)")
     ap.add_argument("--section", choices=["single_view_hard", "rsmss", "uniform_512", "serving"],
                     help="run only this extra section (for profiling) and print it as one JSON line")
     args = ap.parse_args()
@@ -783,7 +794,8 @@ def main():
 
     # ---- headline: the batched workload, one graph replay per step --------
     bf = BatchedFrame(torch, rb)
-    h = batched_headline(torch, rb, bf, args.steps, args.warmup)
+    fixed = tuple(int(x) for x in args.tuning.split(",")) if args.tuning else None
+    h = batched_headline(torch, rb, bf, args.steps, args.warmup, fixed_tuning=fixed)
     frame_bytes = bf.frame_bytes(rb)
     value = bf.n_frag * args.steps / h["wall_s"]
     achieved = frame_bytes / (h["avg_kernel_ms"] * 1e-3) / 1e9
@@ -810,6 +822,7 @@ def main():
             "jobs": len(bf.jobs),
             "resident_bytes": bf.resident_bytes,
             "tuning": tune,
+            "tuning_source": "fixed (--tuning)" if fixed else "autotuned",
         },
         "plain_per_view": h["plain_per_view"],
         "batched_eager": h["batched_eager"],

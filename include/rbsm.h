@@ -201,7 +201,9 @@ int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream);
  * stream with HIP events and keeps the fastest, searching one axis after the
  * other: tile width x launch form (one workgroup per tile or persistent),
  * then (one workgroup per tile) the XCD chunking, then LDS capacity, then
- * apron, then (one workgroup per tile) the walk blocking.  The
+ * apron, then (one workgroup per tile) the walk blocking; a candidate
+ * replaces the best only when it is more than 2% faster, so near-ties keep
+ * the earlier choice in this order.  The
  * choice is cached in the process under a key of the device (architecture,
  * CU count) and the plan's job layout (per job: fragments, view width, map
  * size and pitch, MAXDIST, mode); a later call with the same key applies the

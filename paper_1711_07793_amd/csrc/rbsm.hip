@@ -728,6 +728,7 @@ int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_
     float best_ms = 1e30f;
     int status = RBSM_OK;
     // time one candidate: a warm-up launch, then reps launches between events
+    constexpr float kTuneMargin = 0.02f;
     auto trial = [&](const rbsm_tuning &cand) {
         if (status != RBSM_OK) return;
         if ((status = rbsm_plan_set_tuning(plan, &cand)) != RBSM_OK) return;
@@ -741,7 +742,10 @@ int rbsm_plan_autotune(rbsm_plan *plan, hipStream_t stream, int32_t reps, int32_
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
+        // a candidate replaces the best only when it is faster by more than
+        // kTuneMargin: near-ties keep the earlier (search-order) choice, so
+        // timing noise does not flip the tuning from run to run
+        if (ms < best_ms * (1.0f - kTuneMargin)) {
             best_ms = ms;
             best = plan->tune;
         }
