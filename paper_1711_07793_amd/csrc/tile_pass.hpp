@@ -884,7 +884,11 @@ struct TileConfig {
     int chunk_log2;  // tiles dealt to XCDs in chunks of 2^chunk_log2; < 0: contiguous ranges
 };
 
-constexpr TileConfig kDefaultTile{32, 1, 2048, 0, -1};
+// Default: 32x32 tiles, a 1-texel apron, 2048 texels of LDS, one workgroup per
+// tile, tiles dealt to XCDs in chunks of 8 (measured on frames streamed from
+// HBM: a 4K RSMSS frame 12% faster than with one contiguous range of tiles per
+// XCD, a 1080p hard frame the same).
+constexpr TileConfig kDefaultTile{32, 1, 2048, 0, 3};
 constexpr int kMaxChunkLog2 = 12;
 
 // Persistent launches are built for the default walk blocking only.
