@@ -63,6 +63,7 @@ struct Staged {
     const float *lds;
     int bx0, by0, bw, bh;  // window origin (may be -apron) and size
     bool on;
+    bool inside;           // every fragment texel lies in the map (no clamps needed)
 };
 
 __device__ __forceinline__ int clampi(int x, int n) { return min(max(x, 0), n - 1); }
@@ -209,7 +210,7 @@ struct TileShared {
 // Minimum over the 64 lanes of a wave, returned to every lane: a DPP
 // reduction (rows of 16 by shifts, then the row broadcasts), 6 VALU
 // instructions where a shuffle tree takes about 30.  The box reduction feeds
-// it values in [-1, 65535] or INT32_MAX, so negating one is safe.
+// it values in [-2^20, 2^20] or INT32_MAX, and negates only the former.
 __device__ __forceinline__ int wave_min(int x) {
     x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x111, 0xf, 0xf, false));  // row_shr:1
     x = min(x, __builtin_amdgcn_update_dpp(INT32_MAX, x, 0x112, 0xf, 0xf, false));  // row_shr:2
@@ -233,6 +234,8 @@ __device__ __forceinline__ int opaque_tid() {
 // Where a thread's 4 pixels of tile `tile_id` sit: a TW x (1024/TW) tile of a
 // row-major image of width vw (flat mode: vw = n, TW = 1024), each thread 4
 // consecutive pixels of one row.  Tile and image counts stay below 2^31.
+// Every index a thread forms is below n + TH * vw + TW; when that is below
+// 2^31 (a uniform test) the per-thread arithmetic is 32-bit.
 template <int TW>
 struct TilePos {
     int64_t tyi, txi, px0, k0;
@@ -242,10 +245,18 @@ struct TilePos {
         constexpr int LPR = TW / kF;
         tyi = (int64_t)((uint32_t)tile_id / (uint32_t)tiles_x);
         txi = tile_id - tyi * tiles_x;
-        px0 = txi * TW + (int64_t)(t % LPR) * kF;
-        k0 = (tyi * TH + t / LPR) * vw + px0;
-        const int64_t lim = min(vw - px0, n - k0);
-        avail = (int)max(min(lim, (int64_t)kF), (int64_t)0);
+        if (n + (int64_t)TH * vw + TW < ((int64_t)1 << 31)) {
+            const int px = (int)txi * TW + (t % LPR) * kF;
+            const int k = ((int)tyi * TH + t / LPR) * (int)vw + px;
+            px0 = px;
+            k0 = k;
+            avail = max(min(min((int)vw - px, (int)n - k), kF), 0);
+        } else {
+            px0 = txi * TW + (int64_t)(t % LPR) * kF;
+            k0 = (tyi * TH + t / LPR) * vw + px0;
+            const int64_t lim = min(vw - px0, n - k0);
+            avail = (int)max(min(lim, (int64_t)kF), (int64_t)0);
+        }
     }
 };
 
@@ -253,9 +264,8 @@ struct TilePos {
 // ones) when the 4 pixels are in range and aligned, else guarded 4-byte loads
 // (zeros where a pixel lies outside the image).
 template <int TW>
-__device__ __forceinline__ void load_tile_frags(const float *__restrict__ frags, int64_t n, int64_t vw,
-                                                int64_t tiles_x, int64_t tile_id, int vec_ok, float (&fr)[3 * kF]) {
-    const TilePos<TW> P(vw, n, tiles_x, tile_id, opaque_tid());
+__device__ __forceinline__ void load_tile_frags(const float *__restrict__ frags, const TilePos<TW> &P, int vec_ok,
+                                                float (&fr)[3 * kF]) {
     bool valid[kF];
 #pragma unroll
     for (int f = 0; f < kF; ++f) valid[f] = f < P.avail;
@@ -303,9 +313,9 @@ struct NoPrefetch {
 template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class Prefetch = NoPrefetch>
 __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__restrict__ frags, int64_t n,
                                                     int64_t vw, int64_t tiles_x, float bias, int maxd, int apron,
-                                                    int cap, int vec_ok, void *__restrict__ out_v, int64_t tile_id,
-                                                    const float (&fr)[3 * kF], TileShared &sh, float *s_tex,
-                                                    bool hard_rt, const Prefetch &prefetch) {
+                                                    int cap, int vec_ok, void *__restrict__ out_v,
+                                                    const TilePos<TW> &P, const float (&fr)[3 * kF], TileShared &sh,
+                                                    float *s_tex, bool hard_rt, const Prefetch &prefetch) {
     const bool HARD = MODE == 2 ? hard_rt : MODE == 1;
     constexpr int TH = kTileF / TW;
     constexpr int LPR = TW / kF;
@@ -320,7 +330,6 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
 
     const int t = opaque_tid();
     const int lane = t & 63, wave = t >> 6;
-    const TilePos<TW> P(vw, n, tiles_x, tile_id, t);
     const int64_t tyi = P.tyi, txi = P.txi, k0 = P.k0;
     const unsigned long long below = (1ull << lane) - 1ull;  // lanes below this one (from the opaque index)
 
@@ -353,17 +362,21 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         for (int f = 0; f < kF; ++f) ad[f] = address(fr[3 * f], fr[3 * f + 1], fr[3 * f + 2], m.W, m.H, bias);
         st.lds = s_tex;
         st.on = false;
+        st.inside = false;
         if (direct) {
             prefetch();
         } else {
-            // clamped texel indices lie in [0, 65535]: -1 marks "no fragment"
+            // the box of the unclamped texel indices (|i|, |j| <= 2^20), clamped
+            // to the map once reduced: clamping is monotone, so the clamped
+            // box is the box of the clamped indices.  The initial imax = -1
+            // clamps to 0 like any negative index, and imin > imax marks a
+            // tile without fragments.
             int imin = INT32_MAX, imax = -1, jmin = INT32_MAX, jmax = -1;
 #pragma unroll
             for (int f = 0; f < kF; ++f)
                 if (valid[f]) {
-                    const int ic = min(max(ad[f].i0, 0), m.W - 1), jc = min(max(ad[f].j0, 0), m.H - 1);
-                    imin = min(imin, ic); imax = max(imax, ic);
-                    jmin = min(jmin, jc); jmax = max(jmax, jc);
+                    imin = min(imin, ad[f].i0); imax = max(imax, ad[f].i0);
+                    jmin = min(jmin, ad[f].j0); jmax = max(jmax, ad[f].j0);
                 }
             imin = wave_min(imin);
             imax = -wave_min(-imax);
@@ -389,11 +402,18 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
             imax = __builtin_amdgcn_readfirstlane(imax);
             jmin = __builtin_amdgcn_readfirstlane(jmin);
             jmax = __builtin_amdgcn_readfirstlane(jmax);
+            const bool any = imin <= imax;
+            // every fragment texel inside the map: the tests need no clamps
+            st.inside = imin >= 0 && imax <= m.W - 1 && jmin >= 0 && jmax <= m.H - 1;
+            imin = min(max(imin, 0), m.W - 1);
+            imax = min(max(imax, 0), m.W - 1);
+            jmin = min(max(jmin, 0), m.H - 1);
+            jmax = min(max(jmax, 0), m.H - 1);
             st.bx0 = imin - apron;
             st.by0 = jmin - apron;
             st.bw = imax - imin + 1 + 2 * apron;
             st.bh = jmax - jmin + 1 + 2 * apron;
-            st.on = imin <= imax && (int64_t)st.bw * st.bh <= (int64_t)cap;
+            st.on = any && (int64_t)st.bw * st.bh <= (int64_t)cap;
             if (st.on) stage_rect(m, s_tex, st.bx0, st.by0, st.bw, st.bh, t);
             __syncthreads();
         }
@@ -406,9 +426,7 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
             // the window holds every fragment texel with a ring of at least
             // one texel, clamped at the map's edge: neighbours at +-1, +-bw
             const lds_float *lt = (const lds_float *)s_tex;
-#pragma unroll
-            for (int f = 0; f < kF; ++f) {
-                const int ti = min(max(ad[f].i0, 0), m.W - 1), tj = min(max(ad[f].j0, 0), m.H - 1);
+            auto read5 = [&](int f, int ti, int tj) {
                 // 24-bit multiply: the row is below the window height and bw below 2^14
                 const int c = valid[f] ? __mul24(tj - st.by0, st.bw) + (ti - st.bx0) : st.bw + 1;
                 tc[f][0] = lt[c - 1];
@@ -416,6 +434,14 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                 tc[f][2] = lt[c + 1];
                 tc[f][3] = lt[c + st.bw];
                 tc[f][4] = lt[c - st.bw];
+            };
+            if (st.inside) {
+#pragma unroll
+                for (int f = 0; f < kF; ++f) read5(f, ad[f].i0, ad[f].j0);
+            } else {
+#pragma unroll
+                for (int f = 0; f < kF; ++f)
+                    read5(f, min(max(ad[f].i0, 0), m.W - 1), min(max(ad[f].j0, 0), m.H - 1));
             }
         } else {
             // the form of the reads is decided once per tile (uniform
@@ -691,10 +717,12 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
                                              int64_t tiles_x, float bias, int maxd, int apron, int cap,
                                              int vec_ok, void *__restrict__ out_v, int64_t tile_id,
                                              TileShared &sh, float *s_tex, bool hard_rt = false) {
+    // the tile's pixel positions, computed once for the loads and the pass
+    const TilePos<TW> P(vw, n, tiles_x, tile_id, opaque_tid());
     float fr[3 * kF];
-    load_tile_frags<TW>(frags, n, vw, tiles_x, tile_id, vec_ok, fr);
-    process_tile_loaded<MODE, TW, WF, WB>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v, tile_id,
-                                          fr, sh, s_tex, hard_rt, NoPrefetch{});
+    load_tile_frags<TW>(frags, P, vec_ok, fr);
+    process_tile_loaded<MODE, TW, WF, WB>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v, P, fr, sh,
+                                          s_tex, hard_rt, NoPrefetch{});
 }
 
 // One job of a launch: a (view, light) pass over its own map, fragments and
@@ -722,7 +750,7 @@ __device__ __forceinline__ void persistent_loop(const JobOf &job_of, int64_t til
     if (g >= tiles) return;
     JobDev J = job_of(g);
     float fr[3 * kF];
-    load_tile_frags<TW>(J.frags, J.n, J.vw, J.tiles_x, g - J.tile_base, J.vec_ok, fr);
+    load_tile_frags<TW>(J.frags, TilePos<TW>(J.vw, J.n, J.tiles_x, g - J.tile_base, opaque_tid()), J.vec_ok, fr);
     for (;;) {
         const int64_t gn = g + G;
         const bool more = gn < tiles;
@@ -730,10 +758,14 @@ __device__ __forceinline__ void persistent_loop(const JobOf &job_of, int64_t til
         if (more) Jn = job_of(gn);
         float fn[3 * kF];
         auto pf = [&]() {
-            if (more) load_tile_frags<TW>(Jn.frags, Jn.n, Jn.vw, Jn.tiles_x, gn - Jn.tile_base, Jn.vec_ok, fn);
+            if (more)
+                load_tile_frags<TW>(Jn.frags, TilePos<TW>(Jn.vw, Jn.n, Jn.tiles_x, gn - Jn.tile_base, opaque_tid()),
+                                    Jn.vec_ok, fn);
         };
         process_tile_loaded<MODE, TW, WF, WB>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap,
-                                              J.vec_ok, J.out, g - J.tile_base, fr, sh, s_tex, J.mode == 0, pf);
+                                              J.vec_ok, J.out,
+                                              TilePos<TW>(J.vw, J.n, J.tiles_x, g - J.tile_base, opaque_tid()), fr,
+                                              sh, s_tex, J.mode == 0, pf);
         if (!more) break;
         g = gn;
         J = Jn;
