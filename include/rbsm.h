@@ -136,8 +136,11 @@ typedef struct {
     int32_t lds_cap;    /* LDS texel capacity per workgroup, 256..12288, or 0:
                            nothing staged, every texel read from global memory */
     int32_t persistent; /* 0: one workgroup per screen tile; 1: only resident
-                           workgroups, each looping over tiles and loading the
-                           next tile's fragments while it works on the current one */
+                           workgroups, looping over tiles: in plans of up to 48
+                           jobs with tiles they take tiles from one queue per XCD;
+                           otherwise (and in the plain entry points) each takes a
+                           fixed share and loads the next tile's fragments while
+                           it works on the current one */
     int32_t walk_first; /* traversal steps every walk takes before unfinished
                            walks are regrouped: 1, 2 or 4 (0 = default 2) */
     int32_t walk_block; /* steps per block of a regrouped walk, read together:

@@ -178,6 +178,7 @@ struct rbsm_plan {
     std::vector<int32_t> rpcf_jobs;  // jobs with kernel_radius > 0, launched before the tile pass
     BatchArgs args{};                // the tile-pass jobs as kernel arguments (when use_args)
     bool use_args = false;
+    int *d_counters = nullptr;       // per-XCD tile queues of a persistent launch (zero between launches)
     int64_t fragments = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -195,8 +196,10 @@ void drop_graph(rbsm_plan *p) {
 void free_tables(rbsm_plan *p) {
     if (p->d_jobs) (void)hipFree(p->d_jobs);
     if (p->d_block_job) (void)hipFree(p->d_block_job);
+    if (p->d_counters) (void)hipFree(p->d_counters);
     p->d_jobs = nullptr;
     p->d_block_job = nullptr;
+    p->d_counters = nullptr;
 }
 
 int64_t plan_grid(const rbsm_plan *p);
@@ -317,8 +320,11 @@ int build_tables(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs, bool kee
     const int64_t base = T.tiles;
     if (!keep_layout || base != plan->blocks) {
         free_tables(plan);
+        constexpr size_t kCounterBytes = 8 * 16 * sizeof(int);  // one queue counter per XCD, 64 bytes apart
         if (hipMalloc(&plan->d_jobs, sizeof(JobDev) * (size_t)n_jobs) != hipSuccess ||
-            hipMalloc(&plan->d_block_job, sizeof(uint16_t) * (size_t)std::max<int64_t>(base, 1)) != hipSuccess) {
+            hipMalloc(&plan->d_block_job, sizeof(uint16_t) * (size_t)std::max<int64_t>(base, 1)) != hipSuccess ||
+            hipMalloc(&plan->d_counters, kCounterBytes) != hipSuccess ||
+            hipMemset(plan->d_counters, 0, kCounterBytes) != hipSuccess) {
             free_tables(plan);
             return fail(RBSM_ERR_HIP, "%s: could not allocate the job tables", fn);
         }
@@ -375,9 +381,9 @@ const void *width_instance(int tw, int wf, int wb) {
 const void *batch_instance(const rbsm_tuning &t, bool args) {
     const int wf = t.walk_first ? t.walk_first : kWalkFirst, wb = t.walk_block ? t.walk_block : kWalkSteps;
     if (t.persistent && args) {
-        if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_arg_loop_kernel<16>);
-        if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_arg_loop_kernel<64>);
-        return reinterpret_cast<const void *>(&batch_arg_loop_kernel<32>);
+        if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_arg_queue_kernel<16>);
+        if (t.tile_w == 64) return reinterpret_cast<const void *>(&batch_arg_queue_kernel<64>);
+        return reinterpret_cast<const void *>(&batch_arg_queue_kernel<32>);
     }
     if (t.persistent) {
         if (t.tile_w == 16) return reinterpret_cast<const void *>(&batch_persistent_kernel<16, kWalkFirst, kWalkSteps>);
@@ -397,8 +403,8 @@ int64_t plan_grid(const rbsm_plan *p) {
 // One batched pass: the RPCF jobs' box-filter kernels, then the tile pass
 // over every tile of the other jobs (tables in device memory).
 void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *bj, const BatchArgs *bargs,
-                   int64_t tiles, int64_t grid, const rbsm_job *host_jobs, const std::vector<int32_t> &rpcf,
-                   hipStream_t stream) {
+                   int *counters, int64_t tiles, int64_t grid, const rbsm_job *host_jobs,
+                   const std::vector<int32_t> &rpcf, hipStream_t stream) {
     for (const int32_t j : rpcf) {
         const rbsm_job &J = host_jobs[j];
         if (J.n == 0) continue;
@@ -416,7 +422,7 @@ void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *
     int apron = tune.apron, cap = tune.lds_cap, chunk = tune.xcd_chunk;
     if (tune.persistent && bargs) {
         int n_tiles = (int)tiles;  // below 2^24
-        void *args[] = {(void *)bargs, (void *)&n_tiles, (void *)&apron, (void *)&cap, (void *)&chunk};
+        void *args[] = {(void *)bargs, (void *)&n_tiles, (void *)&apron, (void *)&cap, (void *)&chunk, (void *)&counters};
         (void)hipLaunchKernel(k, dim3((unsigned)grid), dim3(kT), args, lds, stream);
     } else if (!tune.persistent && bargs) {
         void *args[] = {(void *)bargs, (void *)&apron, (void *)&cap, (void *)&chunk};
@@ -431,8 +437,8 @@ void launch_tables(const rbsm_tuning &tune, const JobDev *jobs, const uint16_t *
 }
 
 void launch_batch(const rbsm_plan *p, hipStream_t stream) {
-    launch_tables(p->tune, p->d_jobs, p->d_block_job, p->use_args ? &p->args : nullptr, p->blocks, p->grid,
-                  p->jobs.data(), p->rpcf_jobs, stream);
+    launch_tables(p->tune, p->d_jobs, p->d_block_job, p->use_args ? &p->args : nullptr, p->d_counters, p->blocks,
+                  p->grid, p->jobs.data(), p->rpcf_jobs, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,7 +1158,7 @@ int rbsm_batch_launch_noalloc(const rbsm_job *jobs, int32_t n_jobs, const rbsm_t
     const size_t lds = (size_t)t.lds_cap * sizeof(float);
     const int64_t grid =
         t.persistent ? std::min<int64_t>(T.tiles, resident_groups(batch_instance(t, false), lds)) : T.tiles;
-    launch_tables(t, d_jobs, d_bj, nullptr, T.tiles, grid, jobs, T.rpcf, stream);
+    launch_tables(t, d_jobs, d_bj, nullptr, nullptr, T.tiles, grid, jobs, T.rpcf, stream);
     return launched(fn);
 }
 

@@ -879,20 +879,39 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     arg_tile<TW, WF, WB>(a, xcd_chunked(blockIdx.x, gridDim.x, chunk_log2), apron, cap, sh, s_tex);
 }
 
-// The same pass with resident workgroups (grid G, a multiple of 8) looping
-// over the launch's tiles, so no workgroup waits to be dispatched: workgroup
-// b takes the virtual blocks b, b + G, b + 2G, ... (all on b's XCD) and
-// processes the tiles xcd_chunked deals to them.  Nothing is carried from one
-// tile to the next, so the loop fits the one-shot kernel's 64 VGPRs.
+// The same pass with resident workgroups taking tiles from queues: one
+// counter per XCD (workgroup b runs on XCD b mod 8) hands out that XCD's
+// virtual blocks x, x + 8, x + 16, ... in order, and xcd_chunked maps them to
+// tiles, so every XCD works through its own chunks (L2 locality) while its
+// workgroups balance dynamically.  Thread 0 fetches the next index while the
+// workgroup works on the current tile.  Each counter is fetched once per
+// virtual block plus once per workgroup that stops; the fetch that returns
+// the last of those values is the last use of the counter in the launch, and
+// its workgroup clears it for the next launch (graph replays included).
 template <int TW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_arg_loop_kernel(
-    const BatchArgs a, int tiles, int apron, int cap, int chunk_log2) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_arg_queue_kernel(
+    const BatchArgs a, int tiles, int apron, int cap, int chunk_log2, int *__restrict__ counters) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
-    for (int v = blockIdx.x; v < tiles; v += gridDim.x) {
-        arg_tile<TW, kWalkFirst, kWalkSteps>(a, xcd_chunked(v, tiles, chunk_log2), apron, cap, sh, s_tex);
-        __syncthreads();  // the next tile reuses the shared state
+    __shared__ int s_next;
+    const int x = blockIdx.x & 7;
+    const int n_x = (tiles - x + 7) >> 3;            // virtual blocks x + 8k below tiles
+    const int g_x = ((int)gridDim.x - x + 7) >> 3;   // workgroups with b mod 8 == x
+    const int last = n_x + g_x - 1;                  // the counter's final value handed out
+    int *ctr = counters + 16 * x;                    // counters 64 bytes apart
+    if (threadIdx.x == 0) s_next = atomicAdd(ctr, 1);
+    __syncthreads();
+    int k = s_next;
+    while (k < n_x) {
+        int pending = 0;
+        if (threadIdx.x == 0) pending = atomicAdd(ctr, 1);  // the next index, in flight during this tile
+        arg_tile<TW, kWalkFirst, kWalkSteps>(a, xcd_chunked(8 * k + x, tiles, chunk_log2), apron, cap, sh, s_tex);
+        __syncthreads();  // the tile's shared state is free; every thread has read s_next
+        if (threadIdx.x == 0) s_next = pending;
+        __syncthreads();
+        k = s_next;
     }
+    if (threadIdx.x == 0 && k == last) atomicExch(ctr, 0);
 }
 
 // Batched pass with resident workgroups looping over the tiles of every job,
