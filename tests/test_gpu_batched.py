@@ -113,12 +113,15 @@ def test_autotune_and_tunings_never_change_results(rb, workload):
         assert np.array_equal(j["out"].cpu().numpy(), want[k]), k
 
 
-def test_graph_replays_match_eager(rb, workload):
+@pytest.mark.parametrize("tuning", [None, (32, 1, 2048, 1, 0, 0, 3)])  # one workgroup per tile; per-XCD queues
+def test_graph_replays_match_eager(rb, workload, tuning):
     maps, jobs = _device_jobs(rb, workload)
-    plan = rb.Plan(jobs)
-    plan.launch()
+    ref = rb.Plan(jobs)
+    ref.launch()
     torch.cuda.synchronize()
     want = [j["out"].cpu().numpy().copy() for j in jobs]
+    ref.close()
+    plan = rb.Plan(jobs) if tuning is None else rb.Plan(jobs, tuning=tuning)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     plan.capture(s)
@@ -130,6 +133,15 @@ def test_graph_replays_match_eager(rb, workload):
         s.synchronize()
         for k, j in enumerate(jobs):
             assert np.array_equal(j["out"].cpu().numpy(), want[k]), (rep, k)
+    # back-to-back replays (the queue counters must be clear at every start)
+    for j in jobs:
+        j["out"].fill_(7)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        plan.launch(s)
+    s.synchronize()
+    for k, j in enumerate(jobs):
+        assert np.array_equal(j["out"].cpu().numpy(), want[k]), k
     plan.close()
 
 
