@@ -53,8 +53,13 @@ def _plain(rb, j):
     return rb.rsmss_visibility(j["map"], j["frags"], j["params"]).cpu().numpy()
 
 
-def test_batched_equals_plain_per_job(rb, workload):
-    maps, jobs = _device_jobs(rb, workload)
+# 48 jobs with tiles: job records in the kernel arguments; 50: device job tables
+LAYOUTS = pytest.mark.parametrize("extra_flat", [False, True], ids=["48jobs_args", "50jobs_tables"])
+
+
+@LAYOUTS
+def test_batched_equals_plain_per_job(rb, workload, extra_flat):
+    maps, jobs = _device_jobs(rb, workload, extra_flat)
     plan = rb.Plan(jobs)
     assert plan.fragments == sum(j["frags"].numel() // 3 for j in jobs)
     plan.launch()
@@ -79,8 +84,9 @@ def test_batched_against_oracle_on_a_few_jobs(rb, workload):
             assert np.max(np.abs(got - oracle.rsmss(m, h["frags"], h["params"]))) <= 1e-5
 
 
-def test_autotune_and_tunings_never_change_results(rb, workload):
-    maps, jobs = _device_jobs(rb, workload)
+@LAYOUTS
+def test_autotune_and_tunings_never_change_results(rb, workload, extra_flat):
+    maps, jobs = _device_jobs(rb, workload, extra_flat)
     plan = rb.Plan(jobs)
     plan.launch()
     torch.cuda.synchronize()
@@ -113,9 +119,10 @@ def test_autotune_and_tunings_never_change_results(rb, workload):
         assert np.array_equal(j["out"].cpu().numpy(), want[k]), k
 
 
-@pytest.mark.parametrize("tuning", [None, (32, 1, 2048, 1, 0, 0, 3)])  # one workgroup per tile; per-XCD queues
-def test_graph_replays_match_eager(rb, workload, tuning):
-    maps, jobs = _device_jobs(rb, workload)
+@LAYOUTS
+@pytest.mark.parametrize("tuning", [None, (32, 1, 2048, 1, 0, 0, 3)])  # one workgroup per tile; resident
+def test_graph_replays_match_eager(rb, workload, tuning, extra_flat):
+    maps, jobs = _device_jobs(rb, workload, extra_flat)
     ref = rb.Plan(jobs)
     ref.launch()
     torch.cuda.synchronize()
