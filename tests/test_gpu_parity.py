@@ -70,7 +70,7 @@ def test_rsmss_workloads(rb, cfg, small):
     check_soft(c["map"], c["frags"], p, got)
 
 
-def test_rpcf_small_all_and_full_sampled(rb):
+def test_rpcf_small_frame_every_seventh_fragment(rb):
     c = synth.make_config(3, 3003, small=True)
     r = c["light_radius"]
     say(f"rpcf small r={r}")
