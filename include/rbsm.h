@@ -194,7 +194,9 @@ int rbsm_plan_create(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tu
 
 /* Replace the jobs (pointers, depth, bias...) keeping each job's fragment
  * count, view_width and kernel_radius, so the tile layout is unchanged
- * (synchronous copy; call when no launch of the plan is in flight). */
+ * (synchronous copy; call when no launch of the plan is in flight).  A
+ * captured graph is captured again with the new jobs (on a stream the call
+ * creates and destroys), so later replays use them. */
 int rbsm_plan_update(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs);
 
 /* Enqueue one batched pass on stream (graph replay after rbsm_plan_capture). */

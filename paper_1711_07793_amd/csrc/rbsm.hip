@@ -676,7 +676,19 @@ int rbsm_plan_create(const rbsm_job *jobs, int32_t n_jobs, const rbsm_tuning *tu
 
 int rbsm_plan_update(rbsm_plan *plan, const rbsm_job *jobs, int32_t n_jobs) {
     if (!plan) return fail(RBSM_ERR_INVALID_ARG, "rbsm_plan_update: plan is null");
-    return build_tables(plan, jobs, n_jobs, true);
+    const bool had_graph = plan->exec != nullptr;
+    const int st = build_tables(plan, jobs, n_jobs, true);
+    if (st != RBSM_OK || !had_graph) return st;
+    // a captured graph holds the launches' arguments (job records, RPCF job
+    // pointers): capture again, on a stream of the library's own
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        drop_graph(plan);
+        return fail(RBSM_ERR_HIP, "rbsm_plan_update: could not create a stream to capture the plan again");
+    }
+    const int cst = rbsm_plan_capture(plan, s);
+    (void)hipStreamDestroy(s);
+    return cst;
 }
 
 int rbsm_plan_launch(rbsm_plan *plan, hipStream_t stream) {

@@ -174,6 +174,37 @@ def test_update_swaps_buffers_with_the_same_layout(rb, workload):
         plan.update(bad)
 
 
+@LAYOUTS
+def test_update_of_a_captured_plan(rb, workload, extra_flat):
+    """Replays after an update use the new buffers: the plan captures again
+    (its jobs travel in kernel arguments, which a graph holds by value)."""
+    maps, jobs = _device_jobs(rb, workload, extra_flat)
+    plan = rb.Plan(jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    want = [j["out"].cpu().numpy().copy() for j in jobs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    plan.capture(s)
+    jobs2 = []
+    for j in jobs:
+        j2 = dict(j)
+        j2["out"] = torch.zeros_like(j["out"])
+        j2["frags"] = j["frags"].clone()
+        jobs2.append(j2)
+    torch.cuda.synchronize()
+    plan.update(jobs2)
+    for j in jobs:  # the old outputs must not be written again
+        j["out"].fill_(3)
+    torch.cuda.synchronize()
+    plan.launch(s)
+    s.synchronize()
+    for k in range(len(jobs)):
+        assert np.array_equal(jobs2[k]["out"].cpu().numpy(), want[k]), k
+        assert np.all(jobs[k]["out"].cpu().numpy() == 3), k
+    plan.close()
+
+
 def test_pitched_maps(rb):
     """Jobs on maps stored with row padding (pitch > width, NaN padding that
     must never be read), hard and RSMSS, in one plan: each equals the plain
