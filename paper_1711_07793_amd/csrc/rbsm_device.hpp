@@ -40,6 +40,11 @@ typedef float f32x3 __attribute__((ext_vector_type(3), aligned(4)));
 __device__ __forceinline__ f32x3 gld3(const float *p) {
     return *(const __attribute__((address_space(1))) f32x3 *)p;
 }
+// 16-byte load of four consecutive texels at 4-byte alignment (map rows).
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ f32x4u gld4u(const float *p) {
+    return *(const __attribute__((address_space(1))) f32x4u *)p;
+}
 // 16-byte forms through a native vector type (HIP's float4 is a class whose
 // copy takes a generic reference, which would bring the flat access back).
 typedef float f32x4 __attribute__((ext_vector_type(4)));

@@ -71,6 +71,7 @@ __device__ __forceinline__ int clampi(int x, int n) { return min(max(x, 0), n - 
 typedef __attribute__((address_space(3))) float lds_float;  // a float in LDS
 
 constexpr int kStageChunk = 8;  // texels per thread whose loads are in flight together
+constexpr int kStageRows4 = 2;  // 4-texel row groups per thread whose loads are in flight together
 
 // Copy the map window [x0, x0+w) x [y0, y0+h) into dst (row-major, stride w).
 // The window may leave the map by the apron; positions outside it hold the
@@ -84,6 +85,42 @@ constexpr int kStageChunk = 8;  // texels per thread whose loads are in flight t
 //    row compare and an LDS address add;
 //  - otherwise the threads stride over the window with clamped coordinates.
 __device__ __forceinline__ void stage_rect(const MapView &m, float *dst, int x0, int y0, int w, int h, int t) {
+    const int ng = (w + 3) >> 2;  // groups of 4 texels per window row
+    if (ng <= kT && x0 >= 0 && x0 + 4 * ng <= m.W && y0 >= 0 && y0 + h <= m.H &&
+        (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u)) {
+        // inside the map with whole groups: every thread owns one group of
+        // 4 columns (one 16-byte load per row, dword aligned) and every
+        // (kT / ng)-th row; rows past the window re-read the thread's first
+        // row and are not stored, columns past it are not stored
+        const int rpr = kT / ng;
+        const int r0 = t / ng, g = t - r0 * ng;
+        if (r0 >= rpr) return;
+        const char *base8 = (const char *)m.t;
+        const unsigned pitch4 = 4u * (unsigned)m.pitch;
+        const unsigned col4 = 4u * (unsigned)(x0 + 4 * g);
+        const int c0 = 4 * g;
+        for (int r = r0; r < h; r += rpr * kStageRows4) {
+            f32x4u v[kStageRows4];
+#pragma unroll
+            for (int u = 0; u < kStageRows4; ++u) {
+                const int row = r + u * rpr;
+                const unsigned y = (unsigned)(y0 + (row < h ? row : r));
+                v[u] = gld4u((const float *)(base8 + (y * pitch4 + col4)));
+            }
+#pragma unroll
+            for (int u = 0; u < kStageRows4; ++u) {
+                const int row = r + u * rpr;
+                if (row < h) {
+                    float *d = dst + row * w + c0;
+                    d[0] = v[u].x;
+                    if (c0 + 1 < w) d[1] = v[u].y;
+                    if (c0 + 2 < w) d[2] = v[u].z;
+                    if (c0 + 3 < w) d[3] = v[u].w;
+                }
+            }
+        }
+        return;
+    }
     if (w <= kT && (int64_t)m.pitch * m.H <= (int64_t)(0xFFFFFFFFu / 4u)) {
         const int rpi = kT / w;  // rows per round
         const int c = t % w, r0 = t / w;
