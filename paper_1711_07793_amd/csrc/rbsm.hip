@@ -215,16 +215,18 @@ struct HostTables {
     std::vector<uint16_t> block_job;
     std::vector<int32_t> rpcf;
     int64_t tiles = 0, frags = 0;
+    int tile_w = 32;
 };
 
 // The jobs with tiles as kernel-argument records, when there are at most
-// kArgJobsMax of them and every pitch fits 32 bits.
+// kArgJobsMax of them, every pitch fits 32 bits and every job fits the 32-bit
+// index form of the pass.
 bool make_args(const HostTables &T, BatchArgs *a) {
     int k = 0;
     for (size_t j = 0; j < T.dev.size(); ++j) {
         if (T.job_tiles[j] == 0) continue;
         const JobDev &D = T.dev[j];
-        if (k == kArgJobsMax || D.m.pitch > (int64_t)INT32_MAX) return false;
+        if (k == kArgJobsMax || D.m.pitch > (int64_t)INT32_MAX || !index32(D.n, D.vw, T.tile_w)) return false;
         JobArg &A = a->jobs[k];
         A.t = D.m.t;
         A.frags = D.frags;
@@ -254,6 +256,7 @@ int make_tables(const char *fn, const rbsm_job *jobs, int32_t n_jobs, int tile_w
         return fail(RBSM_ERR_INVALID_ARG, "%s: job count differs from the plan", fn);
     T.dev.assign(n_jobs, JobDev{});
     T.job_tiles.assign(n_jobs, 0);
+    T.tile_w = tile_w;
     T.block_job.clear();
     T.rpcf.clear();
     int64_t base = 0, frags = 0;

@@ -139,8 +139,9 @@ __global__ __launch_bounds__(kCompT) void composite_batch_kernel(const CompArgs 
 
 // The batched tile pass of a scheduling step, one launch per chunk of jobs of
 // either mode: each tile runs the steps of the single-view pass, with its
-// occupancy (64 VGPRs, 8 workgroups per CU at the default LDS capacity).
-template <int TW>
+// occupancy (64 VGPRs, 8 workgroups per CU at the default LDS capacity).  IX
+// = int when every job of the launch fits the 32-bit index form (index32).
+template <int TW, class IX>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void serve_kernel(const ServeArgs a,
                                                                                               int apron, int cap) {
     extern __shared__ float s_tex[];
@@ -148,8 +149,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, kServeChunkLog2);
     const int j = find_job(a.first, a.n_jobs, g);
     const JobDev &J = a.jobs[j];
-    process_tile<2, TW>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                        g - a.first[j], sh, s_tex, J.mode == 0);
+    process_tile<2, TW, kWalkFirst, kWalkSteps, IX>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap,
+                                                    J.vec_ok, J.out, g - a.first[j], sh, s_tex, J.mode == 0);
 }
 
 }  // namespace rbsm
@@ -347,6 +348,7 @@ bool rbsm_engine::step_launch() {
         for (size_t c0 = 0; c0 < list.size() && e == hipSuccess; c0 += rbsm::kArgJobs) {
             rbsm::ServeArgs A{};
             int64_t tiles = 0;
+            bool ix32 = true;
             for (size_t c = c0; c < list.size() && c < c0 + rbsm::kArgJobs; ++c) {
                 const EngineReq *R = list[c].first;
                 const rbsm_request &q = R->req;
@@ -366,12 +368,17 @@ bool rbsm_engine::step_launch() {
                 D.mode = L.mode;
                 D.vec_ok = ((uintptr_t)D.frags % 16 == 0) && ((uintptr_t)D.out % (L.mode == 0 ? 4 : 16) == 0) &&
                            (lay.vw % 4 == 0);
+                ix32 = ix32 && rbsm::index32(q.n, lay.vw, rbsm::kServeTileW);
                 A.first[A.n_jobs++] = tiles;
                 tiles += lay.tiles;
             }
             if (tiles == 0) continue;
-            hipLaunchKernelGGL((rbsm::serve_kernel<rbsm::kServeTileW>), dim3((unsigned)tiles), dim3(kT), lds,
-                               s_compute, A, kDefaultTile.apron, kDefaultTile.cap);
+            if (ix32)
+                hipLaunchKernelGGL((rbsm::serve_kernel<rbsm::kServeTileW, int>), dim3((unsigned)tiles), dim3(kT), lds,
+                                   s_compute, A, kDefaultTile.apron, kDefaultTile.cap);
+            else
+                hipLaunchKernelGGL((rbsm::serve_kernel<rbsm::kServeTileW, int64_t>), dim3((unsigned)tiles), dim3(kT),
+                                   lds, s_compute, A, kDefaultTile.apron, kDefaultTile.cap);
         }
     }
     for (const auto &rj : rpcf_jobs) {

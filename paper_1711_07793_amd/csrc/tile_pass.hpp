@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rbsm.h"
 #include "rbsm_device.hpp"
@@ -268,30 +269,54 @@ __device__ __forceinline__ int opaque_tid() {
     return t;
 }
 
+// Every fragment index a tile's threads form (padding pixels included) is
+// below n + TH * vw + TW.  Below kIndex32 the tile runs in the 32-bit form:
+// indices are 32-bit and buffers are addressed by unsigned 32-bit byte
+// offsets from their base (12 bytes per fragment stay below 2^32), which
+// takes about a twentieth of the pass's VALU instructions and the scalar
+// registers of the 64-bit index pairs (those otherwise spill to VGPR lanes).
+constexpr int64_t kIndex32 = (int64_t)1 << 28;
+
+__host__ __device__ inline bool index32(int64_t n, int64_t vw, int tw) {
+    return n + (int64_t)(kTileF / tw) * vw + tw < kIndex32;
+}
+
+// Element k of buffer p: in the 32-bit form (IX = int) an unsigned byte
+// offset from the base.
+template <class IX, class T>
+__device__ __forceinline__ T *at(T *p, IX k) {
+    if constexpr (sizeof(IX) == 4) {
+        using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+        return reinterpret_cast<T *>(reinterpret_cast<C *>(p) + (unsigned)k * (unsigned)sizeof(T));
+    } else {
+        return p + k;
+    }
+}
+
 // Where a thread's 4 pixels of tile `tile_id` sit: a TW x (1024/TW) tile of a
 // row-major image of width vw (flat mode: vw = n, TW = 1024), each thread 4
 // consecutive pixels of one row.  Tile and image counts stay below 2^31.
-// Every index a thread forms is below n + TH * vw + TW; when that is below
-// 2^31 (a uniform test) the per-thread arithmetic is 32-bit.
-template <int TW>
+// IX = int: the caller has checked index32.  IX = int64_t: when every index
+// is below 2^31 (a uniform test) the per-thread arithmetic is still 32-bit.
+template <int TW, class IX = int64_t>
 struct TilePos {
-    int64_t tyi, txi, px0, k0;
+    IX tyi, txi, px0, k0;
     int avail;  // how many of the thread's 4 pixels are in the image (0..4)
     __device__ __forceinline__ TilePos(int64_t vw, int64_t n, int64_t tiles_x, int64_t tile_id, int t) {
         constexpr int TH = kTileF / TW;
         constexpr int LPR = TW / kF;
-        tyi = (int64_t)((uint32_t)tile_id / (uint32_t)tiles_x);
-        txi = tile_id - tyi * tiles_x;
-        if (n + (int64_t)TH * vw + TW < ((int64_t)1 << 31)) {
+        tyi = (IX)((uint32_t)tile_id / (uint32_t)tiles_x);
+        txi = (IX)(tile_id - (int64_t)tyi * tiles_x);
+        if (sizeof(IX) == 4 || n + (int64_t)TH * vw + TW < ((int64_t)1 << 31)) {
             const int px = (int)txi * TW + (t % LPR) * kF;
             const int k = ((int)tyi * TH + t / LPR) * (int)vw + px;
             px0 = px;
             k0 = k;
             avail = max(min(min((int)vw - px, (int)n - k), kF), 0);
         } else {
-            px0 = txi * TW + (int64_t)(t % LPR) * kF;
-            k0 = (tyi * TH + t / LPR) * vw + px0;
-            const int64_t lim = min(vw - px0, n - k0);
+            px0 = (IX)((int64_t)txi * TW + (int64_t)(t % LPR) * kF);
+            k0 = (IX)(((int64_t)tyi * TH + t / LPR) * vw + px0);
+            const int64_t lim = min(vw - (int64_t)px0, n - (int64_t)k0);
             avail = (int)max(min(lim, (int64_t)kF), (int64_t)0);
         }
     }
@@ -300,14 +325,14 @@ struct TilePos {
 // Fragment loads of one thread for one tile: one 48-byte load (three 16-byte
 // ones) when the 4 pixels are in range and aligned, else guarded 4-byte loads
 // (zeros where a pixel lies outside the image).
-template <int TW>
-__device__ __forceinline__ void load_tile_frags(const float *__restrict__ frags, const TilePos<TW> &P, int vec_ok,
+template <int TW, class IX>
+__device__ __forceinline__ void load_tile_frags(const float *__restrict__ frags, const TilePos<TW, IX> &P, int vec_ok,
                                                 float (&fr)[3 * kF]) {
     bool valid[kF];
 #pragma unroll
     for (int f = 0; f < kF; ++f) valid[f] = f < P.avail;
     if (vec_ok && valid[kF - 1]) {
-        const float4 *p4 = reinterpret_cast<const float4 *>(frags + 3 * P.k0);
+        const float4 *p4 = reinterpret_cast<const float4 *>(at(frags, 3 * P.k0));
         const float4 a = gld4(p4), b = gld4(p4 + 1), c = gld4(p4 + 2);
         fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
         fr[4] = b.x; fr[5] = b.y; fr[6] = b.z; fr[7] = b.w;
@@ -315,10 +340,10 @@ __device__ __forceinline__ void load_tile_frags(const float *__restrict__ frags,
     } else {
 #pragma unroll
         for (int f = 0; f < kF; ++f) {
-            const int64_t k = P.k0 + f;
-            fr[3 * f + 0] = valid[f] ? gld(frags + 3 * k + 0) : 0.0f;
-            fr[3 * f + 1] = valid[f] ? gld(frags + 3 * k + 1) : 0.0f;
-            fr[3 * f + 2] = valid[f] ? gld(frags + 3 * k + 2) : 0.0f;
+            const IX k3 = 3 * (P.k0 + f);
+            fr[3 * f + 0] = valid[f] ? gld(at(frags, k3 + 0)) : 0.0f;
+            fr[3 * f + 1] = valid[f] ? gld(at(frags, k3 + 1)) : 0.0f;
+            fr[3 * f + 2] = valid[f] ? gld(at(frags, k3 + 2)) : 0.0f;
         }
     }
 }
@@ -347,11 +372,11 @@ struct NoPrefetch {
 // read from and by which lane: every result equals the per-fragment listing.
 // MODE: 1 hard pass, 0 RSMSS, 2 either, chosen per call by hard_rt (one code
 // path for workgroups of both modes in one launch).
-template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class Prefetch = NoPrefetch>
-__device__ __forceinline__ void process_tile_loaded(MapView m, const float *__restrict__ frags, int64_t n,
-                                                    int64_t vw, int64_t tiles_x, float bias, int maxd, int apron,
+template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class Prefetch = NoPrefetch, class IX>
+__device__ __forceinline__ void process_tile_loaded(MapView m, const float *__restrict__ frags, int64_t vw64,
+                                                    float bias, int maxd, int apron,
                                                     int cap, int vec_ok, void *__restrict__ out_v,
-                                                    const TilePos<TW> &P, const float (&fr)[3 * kF], TileShared &sh,
+                                                    const TilePos<TW, IX> &P, const float (&fr)[3 * kF], TileShared &sh,
                                                     float *s_tex, bool hard_rt, const Prefetch &prefetch) {
     const bool HARD = MODE == 2 ? hard_rt : MODE == 1;
     constexpr int TH = kTileF / TW;
@@ -367,7 +392,7 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
 
     const int t = opaque_tid();
     const int lane = t & 63, wave = t >> 6;
-    const int64_t tyi = P.tyi, txi = P.txi, k0 = P.k0;
+    const IX tyi = P.tyi, txi = P.txi, k0 = P.k0, vw = (IX)vw64;
     const unsigned long long below = (1ull << lane) - 1ull;  // lanes below this one (from the opaque index)
 
     Staged st;
@@ -549,21 +574,21 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
                 uint32_t packed = 0;
 #pragma unroll
                 for (int f = 0; f < kF; ++f) packed |= (uint32_t)(s[f] ? 1u : 0u) << (8 * f);
-                gst(reinterpret_cast<uint32_t *>(out + k0), packed);
+                gst(reinterpret_cast<uint32_t *>(at(out, k0)), packed);
             } else {
 #pragma unroll
                 for (int f = 0; f < kF; ++f)
-                    if (valid[f] && !edge[f]) gst(out + k0 + f, (uint8_t)(s[f] ? 1 : 0));
+                    if (valid[f] && !edge[f]) gst(at(out, k0 + f), (uint8_t)(s[f] ? 1 : 0));
             }
         } else {
             float *out = static_cast<float *>(out_v);
             if (full && !any_edge) {
-                gst4(reinterpret_cast<float4 *>(out + k0),
+                gst4(reinterpret_cast<float4 *>(at(out, k0)),
                     make_float4(s[0] ? 1.0f : 0.0f, s[1] ? 1.0f : 0.0f, s[2] ? 1.0f : 0.0f, s[3] ? 1.0f : 0.0f));
             } else {
 #pragma unroll
                 for (int f = 0; f < kF; ++f)
-                    if (valid[f] && !edge[f]) gst(out + k0 + f, s[f] ? 1.0f : 0.0f);
+                    if (valid[f] && !edge[f]) gst(at(out, k0 + f), s[f] ? 1.0f : 0.0f);
             }
         }
 
@@ -600,10 +625,10 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
     if (ne == 0) return;
 
     // fragment index of queue entry e
-    auto frag_of = [&](int e) -> int64_t {
+    auto frag_of = [&](int e) -> IX {
         const int slot = q_slot[e];
         const int owner = slot >> 2, f = slot & 3;
-        return (tyi * TH + owner / LPR) * vw + txi * TW + (int64_t)(owner % LPR) * kF + f;
+        return (tyi * TH + owner / LPR) * vw + txi * TW + (IX)(owner % LPR) * kF + f;
     };
     // texel and biased depth of queue entry e (from LDS, or recomputed past
     // kState); the sub-texel position, needed only by the last step, is
@@ -613,8 +638,8 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         if (e < kState) {
             i0 = q_i[e]; j0 = q_j[e]; zb = q_z[e];
         } else {
-            const int64_t k = frag_of(e);
-            const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), gld(frags + 3 * k + 2), m.W, m.H, bias);
+            const IX k3 = 3 * frag_of(e);
+            const Addr b = address(gld(at(frags, k3)), gld(at(frags, k3 + 1)), gld(at(frags, k3 + 2)), m.W, m.H, bias);
             i0 = b.i0; j0 = b.j0; zb = b.zb;
         }
     };
@@ -669,9 +694,9 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         const bool uv = (task & 3) == 0 && e_uv < kState;
         float u = 0.0f, v = 0.0f;
         if (uv) {
-            const int64_t k = frag_of(e_uv);
-            u = gld(frags + 3 * k);
-            v = gld(frags + 3 * k + 1);
+            const IX k3 = 3 * frag_of(e_uv);
+            u = gld(at(frags, k3));
+            v = gld(at(frags, k3 + 1));
         }
         int i0, j0;
         const Walk w = make_walk(task, i0, j0);
@@ -730,36 +755,37 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
 
     // normalize, evaluate and store, one lane per edge fragment
     for (int e = t; e < ne; e += kT) {
-        const int64_t k = frag_of(e);
+        const IX k = frag_of(e);
         float fx, fy;
         if (e < kState) {
             fx = sh.qfx[e];
             fy = sh.qfy[e];
         } else {
-            const Addr b = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), 0.0f, m.W, m.H, bias);
+            const Addr b = address(gld(at(frags, 3 * k)), gld(at(frags, 3 * k + 1)), 0.0f, m.W, m.H, bias);
             fx = b.fx;
             fy = b.fy;
         }
         const bool s = (q_sm[e] & 16u) != 0;
         const Axis axx = normalize_axis(q_rd[e][0], q_rd[e][1], fx);
         const Axis axy = normalize_axis(q_rd[e][3], q_rd[e][2], fy);
-        if (HARD) gst(static_cast<uint8_t *>(out_v) + k, (uint8_t)(vis_hard(axx, axy) != 0.0f ? 1 : 0));
-        else gst(static_cast<float *>(out_v) + k, vis_rsmss(s, axx, axy));
+        if (HARD) gst(at(static_cast<uint8_t *>(out_v), k), (uint8_t)(vis_hard(axx, axy) != 0.0f ? 1 : 0));
+        else gst(at(static_cast<float *>(out_v), k), vis_rsmss(s, axx, axy));
     }
 }
 
-// A tile whose fragments are loaded first (one workgroup per tile).
-template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps>
+// A tile whose fragments are loaded first (one workgroup per tile).  IX =
+// int: the 32-bit form, which the launch has checked with index32.
+template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class IX = int64_t>
 __device__ __forceinline__ void process_tile(MapView m, const float *__restrict__ frags, int64_t n, int64_t vw,
                                              int64_t tiles_x, float bias, int maxd, int apron, int cap,
                                              int vec_ok, void *__restrict__ out_v, int64_t tile_id,
                                              TileShared &sh, float *s_tex, bool hard_rt = false) {
     // the tile's pixel positions, computed once for the loads and the pass
-    const TilePos<TW> P(vw, n, tiles_x, tile_id, opaque_tid());
+    const TilePos<TW, IX> P(vw, n, tiles_x, tile_id, opaque_tid());
     float fr[3 * kF];
     load_tile_frags<TW>(frags, P, vec_ok, fr);
-    process_tile_loaded<MODE, TW, WF, WB>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v, P, fr, sh,
-                                          s_tex, hard_rt, NoPrefetch{});
+    process_tile_loaded<MODE, TW, WF, WB>(m, frags, vw, bias, maxd, apron, cap, vec_ok, out_v, P, fr, sh, s_tex,
+                                          hard_rt, NoPrefetch{});
 }
 
 // One job of a launch: a (view, light) pass over its own map, fragments and
@@ -799,8 +825,7 @@ __device__ __forceinline__ void persistent_loop(const JobOf &job_of, int64_t til
                 load_tile_frags<TW>(Jn.frags, TilePos<TW>(Jn.vw, Jn.n, Jn.tiles_x, gn - Jn.tile_base, opaque_tid()),
                                     Jn.vec_ok, fn);
         };
-        process_tile_loaded<MODE, TW, WF, WB>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap,
-                                              J.vec_ok, J.out,
+        process_tile_loaded<MODE, TW, WF, WB>(J.m, J.frags, J.vw, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
                                               TilePos<TW>(J.vw, J.n, J.tiles_x, g - J.tile_base, opaque_tid()), fr,
                                               sh, s_tex, J.mode == 0, pf);
         if (!more) break;
@@ -814,14 +839,14 @@ __device__ __forceinline__ void persistent_loop(const JobOf &job_of, int64_t til
 // 8 waves per SIMD: 64 VGPRs (no spills) and, with the default LDS capacity,
 // 19 KB of LDS let 8 workgroups share a CU, so a 1080p frame's 2,040 tiles
 // are all resident at once (one round, no second prologue).
-template <bool HARD, int TW>
+template <bool HARD, int TW, class IX>
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void tile_kernel(
     MapView m, const float *__restrict__ frags, int64_t n, int64_t vw, int64_t tiles_x, float bias, int maxd,
     int apron, int cap, int vec_ok, void *__restrict__ out_v, int chunk_log2) {
     extern __shared__ float s_tex[];
     __shared__ TileShared sh;
-    process_tile<HARD, TW>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v,
-                           xcd_chunked(blockIdx.x, gridDim.x, chunk_log2), sh, s_tex);
+    process_tile<HARD, TW, kWalkFirst, kWalkSteps, IX>(m, frags, n, vw, tiles_x, bias, maxd, apron, cap, vec_ok, out_v,
+                                                       xcd_chunked(blockIdx.x, gridDim.x, chunk_log2), sh, s_tex);
 }
 
 // The same pass with resident workgroups looping over the tiles (the job is
@@ -856,15 +881,11 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 
 // Batched pass with its job records in the kernel arguments: a workgroup
 // finds its job by a binary search over the jobs' first tiles and reads the
-// record with scalar loads from the argument segment (cached), with no
-// dependent loads from a table in memory (which cost a workgroup about 1.3 us
-// before its fragment loads could start).  For launches of up to
-// kArgJobsMax jobs with tiles.
-// Batched pass with the job records in the kernel arguments: a workgroup
-// finds its job from the kernel-argument segment, which every workgroup reads
-// and so stays in the scalar and L2 caches, instead of two dependent loads of
-// device tables (the tile's job index, then the job record) that miss in each
-// XCD's L2 on first touch.  For batches of at most kArgJobsMax jobs with tiles.
+// record with scalar loads from the argument segment, which every workgroup
+// reads and so stays in the scalar and L2 caches, instead of two dependent
+// loads of device tables (the tile's job index, then the job record; about
+// 1.3 us before a workgroup's fragment loads could start).  For batches of at
+// most kArgJobsMax jobs with tiles, every one in the 32-bit form (index32).
 struct JobArg {
     const float *t;        // map
     const float *frags;
@@ -904,8 +925,8 @@ __device__ __forceinline__ void arg_tile(const BatchArgs &a, int64_t g, int apro
     m.pitch = J.pitch;
     m.W = J.W;
     m.H = J.H;
-    process_tile<2, TW, WF, WB>(m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                                g - J.tile_base, sh, s_tex, J.mode == 0);
+    process_tile<2, TW, WF, WB, int>(m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
+                                     g - J.tile_base, sh, s_tex, J.mode == 0);
 }
 
 template <int TW, int WF = kWalkFirst, int WB = kWalkSteps>
@@ -1025,8 +1046,12 @@ void launch_tiles(const MapView &mv, const float *frags, int64_t n, int64_t vw, 
         hipLaunchKernelGGL((tile_persistent_kernel<HARD, TW>), dim3((unsigned)grid), dim3(kT), lds, stream, J, tiles,
                            cfg.apron, cfg.cap);
     } else {
-        hipLaunchKernelGGL((tile_kernel<HARD, TW>), dim3((unsigned)tiles), dim3(kT), lds, stream, mv, frags, n, vw,
-                           tiles_x, bias, maxd, cfg.apron, cfg.cap, vec, out, cfg.chunk_log2);
+        if (index32(n, vw, TW))
+            hipLaunchKernelGGL((tile_kernel<HARD, TW, int>), dim3((unsigned)tiles), dim3(kT), lds, stream, mv, frags,
+                               n, vw, tiles_x, bias, maxd, cfg.apron, cfg.cap, vec, out, cfg.chunk_log2);
+        else
+            hipLaunchKernelGGL((tile_kernel<HARD, TW, int64_t>), dim3((unsigned)tiles), dim3(kT), lds, stream, mv,
+                               frags, n, vw, tiles_x, bias, maxd, cfg.apron, cfg.cap, vec, out, cfg.chunk_log2);
     }
 }
 

@@ -69,6 +69,32 @@ def test_batched_equals_plain_per_job(rb, workload, extra_flat):
     plan.close()
 
 
+def test_a_job_beyond_the_32_bit_index_form(rb, workload):
+    """A plan whose jobs include one too large for the 32-bit index form
+    (2^28 fragments in a 4096-pixel-wide view) runs with device job tables
+    and the 64-bit form: every job's output is bitwise the plain call's."""
+    maps, jobs = _device_jobs(rb, workload, extra_flat=False)
+    jobs = jobs[:6]
+    c = synth.make_config(1, 1025, small=True)
+    m1 = torch.from_numpy(c["map"]).cuda()
+    n = 1 << 28
+    g = torch.Generator(device="cuda").manual_seed(25)
+    f = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    f[:, 0].uniform_(-0.02, 1.02, generator=g)
+    f[:, 1].uniform_(-0.02, 1.02, generator=g)
+    f[:, 2].uniform_(0.3, 0.95, generator=g)
+    jobs.append(dict(map=m1, frags=f, params=dict(c["params"], view_width=4096), mode=0,
+                     out=torch.empty(n, dtype=torch.uint8, device="cuda")))
+    plan = rb.Plan(jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        assert np.array_equal(j["out"].cpu().numpy(), _plain(rb, j)), k
+    plan.close()
+    del f, jobs
+    torch.cuda.empty_cache()
+
+
 def test_batched_against_oracle_on_a_few_jobs(rb, workload):
     maps, jobs = _device_jobs(rb, workload, extra_flat=False)
     plan = rb.Plan(jobs)

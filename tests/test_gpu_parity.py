@@ -377,6 +377,43 @@ def test_largest_fragment_count(rb):
     torch.cuda.empty_cache()
 
 
+def test_both_index_forms_at_their_boundary(rb):
+    """A 4096-pixel-wide view (32 x 32 tiles) with the most fragments the
+    32-bit index form takes (n + 32 * 4096 + 32 < 2^28: 3.2 GB of fragments,
+    byte offsets up to 3.2e9) and one fragment more (the 64-bit form), hard
+    and RSMSS: sampled outputs, the ragged last row included, against the
+    oracle."""
+    c = synth.make_config(1, 1023, small=True)
+    m = c["map"]
+    vw = 4096
+    n32 = (1 << 28) - 32 * vw - 32 - 1
+    say(f"index forms: generating {n32 + 1} fragments")
+    g = torch.Generator(device="cuda").manual_seed(23)
+    f = torch.empty((n32 + 1, 3), dtype=torch.float32, device="cuda")
+    f[:, 0].uniform_(-0.02, 1.02, generator=g)
+    f[:, 1].uniform_(-0.02, 1.02, generator=g)
+    f[:, 2].uniform_(0.3, 0.95, generator=g)
+    md = dev(m)
+    p = dict(c["params"], view_width=vw)
+    rng = np.random.default_rng(24)
+    for n in (n32, n32 + 1):
+        idx = np.unique(np.concatenate([rng.integers(0, n, 3000), np.arange(n - 5000, n),
+                                        np.arange((1 << 27) - 600, (1 << 27) + 600)]))
+        ti = torch.from_numpy(idx).cuda()
+        fs = f[ti].cpu().numpy()
+        fn = f[:n]
+        say(f"index forms: n = {n} hard")
+        got = rb.rbsm_visibility(md, fn, p)
+        check_hard(m, fs, p, got[ti].cpu().numpy())
+        del got
+        say(f"index forms: n = {n} rsmss")
+        got = rb.rsmss_visibility(md, fn, p)
+        check_soft(m, fs, p, got[ti].cpu().numpy())
+        del got
+    del f
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("horizontal", [True, False])
 def test_long_walks_overflow_the_continuation_queue(rb, horizontal):
     """Stripes one texel wide: every fragment is an edge fragment whose walks
