@@ -37,7 +37,7 @@ __device__ __forceinline__ int64_t xcd_block(int b, int nb) {
 __device__ __forceinline__ int64_t xcd_chunked(int b, int nb, int chunk_log2) {
     if (chunk_log2 < 0) return xcd_block(b, nb);
     const int round = 8 << chunk_log2;
-    const int full = nb / round;
+    const int full = nb >> (3 + chunk_log2);  // nb / round
     if (b >= full * round) return (int64_t)full * round + xcd_block(b - full * round, nb - full * round);
     const int x = b & 7, l = b >> 3;
     const int q = l >> chunk_log2, r = l & ((1 << chunk_log2) - 1);
@@ -904,16 +904,21 @@ struct BatchArgs {
     JobArg jobs[kArgJobsMax];
 };
 
-// The job of launch tile g: binary search over the first tiles in the
-// argument segment, scalar loads that hit the scalar cache (a launch has fewer
-// than 2^24 tiles; g is wave-uniform).
+// The job of launch tile g: the last job whose first tile is at or below g
+// (first tiles increase strictly; a launch has fewer than 2^24 tiles; g is
+// wave-uniform).  Two rounds of scalar loads from the argument segment, where
+// a binary search would chain five: every eighth first tile picks the group of
+// eight, then the group's first tiles pick the job.
 __device__ __forceinline__ int arg_job(const BatchArgs &a, int64_t g) {
+    static_assert(kArgJobsMax % 8 == 0, "groups of eight jobs");
     const int g32 = __builtin_amdgcn_readfirstlane((int)g);
-    int lo = 0;
+    int b = 0;
 #pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-        if (lo + step < kArgJobsMax && a.first[lo + step] <= g32) lo += step;
-    return lo;
+    for (int r = 8; r < kArgJobsMax; r += 8) b = a.first[r] <= g32 ? r : b;
+    int j = b;
+#pragma unroll
+    for (int r = 1; r < 8; ++r) j = a.first[b + r] <= g32 ? b + r : j;
+    return j;
 }
 
 template <int TW, int WF, int WB>
