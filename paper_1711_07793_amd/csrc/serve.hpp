@@ -149,8 +149,9 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, kServeChunkLog2);
     const int j = find_job(a.first, a.n_jobs, g);
     const JobDev &J = a.jobs[j];
-    process_tile<2, TW, kWalkFirst, kWalkSteps, IX>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap,
-                                                    J.vec_ok, J.out, g - a.first[j], sh, s_tex, J.mode == 0);
+    process_tile<2, TW, kWalkFirst, kWalkSteps, IX, true>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron,
+                                                          cap, J.vec_ok, J.out, g - a.first[j], sh, s_tex,
+                                                          J.mode == 0);
 }
 
 }  // namespace rbsm

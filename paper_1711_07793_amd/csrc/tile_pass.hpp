@@ -201,6 +201,18 @@ struct GlobalWalkReader {  // a map under 4 GiB in global memory
     }
 };
 
+struct LdsWalkReader {  // the staged window in LDS (row stride bw)
+    const lds_float *t;   // window base
+    int c, a, b;          // window index of the fixed coordinate, less the moving one's origin
+    int step;             // window index per unit of p
+    __device__ __forceinline__ void operator()(int p, float &tc, float &ta, float &tb) const {
+        const int x = p * step;
+        tc = t[c + x];
+        ta = t[a + x];
+        tb = t[b + x];
+    }
+};
+
 template <int NB, class Reader>
 __device__ __forceinline__ int walk_range(const Reader &rd3, int k0, int k1, int p0, int d, int pmax, float zb, bool s,
                                           bool chk_a, bool chk_b) {
@@ -361,8 +373,9 @@ struct NoPrefetch {
 //  3. edge fragments are compacted with wave ballots into an LDS queue that
 //     keeps their texel, depth, sub-texel position, test and mask;
 //  4. one lane per (edge fragment, direction) takes the walk's first WF
-//     steps from global memory (L2); walks still running are queued again
-//     and continued in blocks of WB steps;
+//     steps from global memory (L2) (with LW: up to WF steps in the staged
+//     window first); walks still running are queued again and continued in
+//     blocks of WB steps from global memory;
 //  5. one lane per edge fragment normalizes, evaluates the visibility
 //     function and stores.
 // `prefetch` runs once, right after the box reduction, every thread of the
@@ -372,7 +385,8 @@ struct NoPrefetch {
 // read from and by which lane: every result equals the per-fragment listing.
 // MODE: 1 hard pass, 0 RSMSS, 2 either, chosen per call by hard_rt (one code
 // path for workgroups of both modes in one launch).
-template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class Prefetch = NoPrefetch, class IX>
+template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, bool LW = false, class Prefetch = NoPrefetch,
+          class IX>
 __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__restrict__ frags, int64_t vw64,
                                                     float bias, int maxd, int apron,
                                                     int cap, int vec_ok, void *__restrict__ out_v,
@@ -644,12 +658,14 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         }
     };
 
-    // walks, one lane per (fragment, direction), straight from global memory
-    // (L2) in blocks of steps whose reads are issued together; staging the
-    // walks' bands in LDS first measured slower.  Most walks stop within a
-    // few steps, so every walk first takes WF steps; the unfinished ones are
-    // compacted into a queue and continued by as few waves as possible
-    // instead of holding every wave that has one of them.
+    // walks, one lane per (fragment, direction), from global memory (L2) in
+    // blocks of steps whose reads are issued together (with LW, the first
+    // steps that lie in the staged window read it instead; staging extra
+    // bands for the walks measured slower).  Most walks stop within a few
+    // steps, so every walk first takes WF steps (with LW, up to WF more past
+    // the window); the unfinished ones are compacted into a queue and
+    // continued by as few waves as possible instead of holding every wave
+    // that has one of them.
     const bool map_32 = (int64_t)m.pitch * m.H * 4 <= (int64_t)0xFFFFFFFFu;  // byte offsets fit 32 bits
     struct Walk {
         GlobalWalkReader r;
@@ -657,8 +673,13 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         float zb;
         bool s, chk_a, chk_b;
     };
-    // walk `task` = 4 e + direction (0 left, 1 right, 2 top, 3 bottom)
-    auto make_walk = [&](int task, int &i0, int &j0) -> Walk {
+    struct WalkLds {
+        LdsWalkReader l;
+        int kin;  // steps 1..kin lie in the staged window
+    };
+    // walk `task` = 4 e + direction (0 left, 1 right, 2 top, 3 bottom); with
+    // LW, lw (if given) receives its reader of the staged window
+    auto make_walk = [&](int task, int &i0, int &j0, WalkLds *lw) -> Walk {
         const int e = task >> 2, dir = task & 3;
         float zb;
         state_of(e, i0, j0, zb);
@@ -684,6 +705,34 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         w.r.a = (unsigned)fa * fmul;
         w.r.b = (unsigned)fb * fmul;
         w.r.step4 = horiz ? 4u : 4u * (unsigned)m.pitch;
+        // The walk's clamped positions move monotonically away from the
+        // fragment's clamped texel, which lies in the box: they stay in the
+        // window [lo, hi] up to step kin >= 1 (every step when the window
+        // reaches the map's edge on that side).  The fixed coordinates are
+        // within one texel of the box, inside the apron.
+        if constexpr (LW) {
+            if (lw) {
+                lw->kin = 0;
+                if (st.on) {
+                    const int lo = horiz ? st.bx0 : st.by0;
+                    const int hi = lo + (horiz ? st.bw : st.bh) - 1;
+                    const int kin = w.d > 0 ? (hi >= w.pmax ? maxd : hi - w.p0) : (lo <= 0 ? maxd : w.p0 - lo);
+                    lw->kin = min(kin, maxd);
+                    lw->l.t = (const lds_float *)s_tex;
+                    if (horiz) {
+                        lw->l.c = (fc - st.by0) * st.bw - st.bx0;
+                        lw->l.a = (fa - st.by0) * st.bw - st.bx0;
+                        lw->l.b = (fb - st.by0) * st.bw - st.bx0;
+                        lw->l.step = 1;
+                    } else {
+                        lw->l.c = fc - st.bx0 - st.by0 * st.bw;
+                        lw->l.a = fa - st.bx0 - st.by0 * st.bw;
+                        lw->l.b = fb - st.bx0 - st.by0 * st.bw;
+                        lw->l.step = st.bw;
+                    }
+                }
+            }
+        }
         return w;
     };
     const int first = min(WF, maxd);
@@ -699,16 +748,26 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
             v = gld(at(frags, k3 + 1));
         }
         int i0, j0;
-        const Walk w = make_walk(task, i0, j0);
+        WalkLds wl;
+        const Walk w = make_walk(task, i0, j0, LW ? &wl : nullptr);
         int rd;
         bool queued = false;  // continued after the barrier
         if (map_32) {
-            rd = walk_range<WF>(w.r, 1, first, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
-            if (rd == 0 && first < maxd) {
+            int kg = first;  // the last step taken before the continuation
+            if constexpr (LW) {
+                // up to WF steps in the window, then up to WF from global memory
+                const int kl = min(wl.kin, first);
+                rd = st.on ? walk_range<WF>(wl.l, 1, kl, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b) : 0;
+                kg = min(kl + WF, maxd);
+                if (rd == 0) rd = walk_range<WF>(w.r, kl + 1, kg, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
+            } else {
+                rd = walk_range<WF>(w.r, 1, first, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
+            }
+            if (rd == 0 && kg < maxd) {
                 const int slot = atomicAdd(&sh.ncont, 1);
                 queued = slot < kCont;
                 if (queued) sh.cont[slot] = (int16_t)task;
-                else rd = walk_range<WB>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
+                else rd = walk_range<WB>(w.r, kg + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
             }
             if (rd == 0) rd = -(maxd + 1);
         } else {
@@ -746,8 +805,10 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
         for (int c = t; c < nc; c += kT) {
             const int task = sh.cont[c];
             int i0, j0;
-            const Walk w = make_walk(task, i0, j0);
-            const int rd = walk_range<WB>(w.r, first + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
+            WalkLds wl;
+            const Walk w = make_walk(task, i0, j0, LW ? &wl : nullptr);
+            const int kg = LW ? min(min(wl.kin, first) + WF, maxd) : first;
+            const int rd = walk_range<WB>(w.r, kg + 1, maxd, w.p0, w.d, w.pmax, w.zb, w.s, w.chk_a, w.chk_b);
             q_rd[task >> 2][task & 3] = (int8_t)(rd != 0 ? rd : -(maxd + 1));
         }
         __syncthreads();
@@ -774,8 +835,14 @@ __device__ __forceinline__ void process_tile_loaded(MapView m, const float *__re
 }
 
 // A tile whose fragments are loaded first (one workgroup per tile).  IX =
-// int: the 32-bit form, which the launch has checked with index32.
-template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class IX = int64_t>
+// int: the 32-bit form, which the launch has checked with index32.  LW: each
+// walk first takes up to WF steps in the staged window, then up to WF from
+// global memory, so a wave whose walks all stop in the window makes no global
+// round trip (batched and serving launches, where many tiles share the GPU:
+// a batched frame measured 2% faster; a single frame's launch, whose time is
+// its slowest tiles, measured up to 8% slower in hard mode, so it keeps one
+// block of global steps).
+template <int MODE, int TW, int WF = kWalkFirst, int WB = kWalkSteps, class IX = int64_t, bool LW = false>
 __device__ __forceinline__ void process_tile(MapView m, const float *__restrict__ frags, int64_t n, int64_t vw,
                                              int64_t tiles_x, float bias, int maxd, int apron, int cap,
                                              int vec_ok, void *__restrict__ out_v, int64_t tile_id,
@@ -784,8 +851,8 @@ __device__ __forceinline__ void process_tile(MapView m, const float *__restrict_
     const TilePos<TW, IX> P(vw, n, tiles_x, tile_id, opaque_tid());
     float fr[3 * kF];
     load_tile_frags<TW>(frags, P, vec_ok, fr);
-    process_tile_loaded<MODE, TW, WF, WB>(m, frags, vw, bias, maxd, apron, cap, vec_ok, out_v, P, fr, sh, s_tex,
-                                          hard_rt, NoPrefetch{});
+    process_tile_loaded<MODE, TW, WF, WB, LW>(m, frags, vw, bias, maxd, apron, cap, vec_ok, out_v, P, fr, sh, s_tex,
+                                              hard_rt, NoPrefetch{});
 }
 
 // One job of a launch: a (view, light) pass over its own map, fragments and
@@ -875,8 +942,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int64_t g = xcd_chunked(blockIdx.x, gridDim.x, chunk_log2);
     const JobDev J = jobs[block_job[g]];
     const int64_t tile = g - J.tile_base;
-    process_tile<2, TW, WF, WB>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out, tile,
-                                sh, s_tex, J.mode == 0);
+    process_tile<2, TW, WF, WB, int64_t, true>(J.m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap,
+                                               J.vec_ok, J.out, tile, sh, s_tex, J.mode == 0);
 }
 
 // Batched pass with its job records in the kernel arguments: a workgroup
@@ -930,8 +997,8 @@ __device__ __forceinline__ void arg_tile(const BatchArgs &a, int64_t g, int apro
     m.pitch = J.pitch;
     m.W = J.W;
     m.H = J.H;
-    process_tile<2, TW, WF, WB, int>(m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok, J.out,
-                                     g - J.tile_base, sh, s_tex, J.mode == 0);
+    process_tile<2, TW, WF, WB, int, true>(m, J.frags, J.n, J.vw, J.tiles_x, J.bias, J.maxd, apron, cap, J.vec_ok,
+                                           J.out, g - J.tile_base, sh, s_tex, J.mode == 0);
 }
 
 template <int TW, int WF = kWalkFirst, int WB = kWalkSteps>
