@@ -747,6 +747,13 @@ def rsmss_section(torch, rb, steps: int):
         "workload": f"RPCF radius {r3} ({(2 * r3 + 1) ** 2} RSMSS terms per fragment) on the RSMSS frames",
         "kernel_radius": r3, "fragments_per_s": fr3.n * steps_r / wr, "ms_per_step": wr * 1e3 / steps_r,
         "avg_kernel_ms": ar, "terms_per_s": fr3.n * (2 * r3 + 1) ** 2 / (ar * 1e-3)}
+    # the range of light radii the workload draws from (3-15), same frames
+    sweep = {}
+    for r in (3, 8, 15):
+        _, a_r, _ = time_pass(torch, rb, lib, "rsmss_visibility", fr3, dict(fr3.params, kernel_radius=r),
+                              max(5, steps // 40), 2)
+        sweep[str(r)] = {"avg_kernel_ms": a_r, "terms_per_s": fr3.n * (2 * r + 1) ** 2 / (a_r * 1e-3)}
+    out["rpcf"]["by_radius"] = sweep
     return out
 
 
