@@ -947,8 +947,8 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 }
 
 // Batched pass with its job records in the kernel arguments: a workgroup
-// finds its job by a binary search over the jobs' first tiles and reads the
-// record with scalar loads from the argument segment, which every workgroup
+// finds its job from the jobs' first tiles (arg_job) and reads the record
+// with scalar loads from the argument segment, which every workgroup
 // reads and so stays in the scalar and L2 caches, instead of two dependent
 // loads of device tables (the tile's job index, then the job record; about
 // 1.3 us before a workgroup's fragment loads could start).  For batches of at
