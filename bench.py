@@ -23,6 +23,7 @@ import ctypes
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -37,13 +38,21 @@ ROTATE_BYTES = 512 << 20
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "batch_arg_kernel_16maps_8views_traffic.md")
 
 
+def code_tokens(text: str) -> str:
+    """C++ source without its comments and with runs of white space made one
+    space: what the compiler sees, so edits of comments keep the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources that define the hard-pass kernel (tile pass and the
-    per-fragment device helpers)."""
+    """Hash of the code (comments aside) that defines the tile-pass kernels:
+    the tile pass and the per-fragment device helpers."""
     h = hashlib.sha256()
     for rel in ("paper_1711_07793_amd/csrc/tile_pass.hpp", "paper_1711_07793_amd/csrc/rbsm_device.hpp"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 
