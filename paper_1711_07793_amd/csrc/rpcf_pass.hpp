@@ -99,8 +99,9 @@ typedef __attribute__((address_space(3))) const char lds_byte;
 // traversal moves along and its two side lines.
 struct BandWalkReader {
     lds_byte *c, *a, *b;
+    unsigned step;  // bytes per unit of p
     __device__ __forceinline__ void operator()(int p, float &tc, float &ta, float &tb) const {
-        const unsigned x = 4u * (unsigned)p;
+        const unsigned x = step * (unsigned)p;
         tc = *(const lds_float *)(c + x);
         ta = *(const lds_float *)(a + x);
         tb = *(const lds_float *)(b + x);
@@ -184,16 +185,19 @@ __device__ __forceinline__ int column_walk_down(uint64_t wl, uint64_t w, uint64_
 // One workgroup per TW x (kRpcfT / TW) pixel tile of a row-major image of
 // width vw (flat: vw = n, TW = kRpcfT).  With R = r + min(maxd, kRpcfReach),
 // the texels every word and the first R - r steps of every traversal read lie
-// in two bands, staged in LDS (with canon() applied) when both fit in `cap`
+// in bands staged in LDS (with canon() applied) when they fit in `cap`
 // texels; longer traversals go on in global memory:
 //   H: rows of the fragments' texel box grown by r+1, columns grown by R
 //      (row-major; horizontal traversals);
-//   V: columns grown by r+1, rows grown by R, stored transposed, each column
-//      contiguous (column words and vertical traversals).
+//   V (VB): columns grown by r+1, rows grown by R, stored transposed, each
+//      column contiguous (column words and vertical traversals).
+// Without V, column words read H down its columns (7 more rows staged for the
+// chunked reads) and vertical traversals use H's rows: half the LDS, so more
+// workgroups per CU, for slower column reads and a shorter vertical reach.
 // Band coordinates are unclamped positions holding clamped texels, so no read
 // clamps.  Otherwise everything reads global memory.  Requires 1 <= r <=
 // kRpcfMaxR.
-template <int TW>
+template <int TW, bool VB>
 __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__restrict__ frags, int64_t n,
                                                       int64_t vw, int64_t tiles_x, float bias, int maxd, int r,
                                                       int cap, float *__restrict__ out) {
@@ -252,11 +256,12 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     // length keeps the transposing stores conflict-free
     const int vx = b0 - r - 1, vy = b2 - R;
     const int vwd = fw + 2 * r + 3, vh = (fh + 2 * R + 1 + 7) | 1;
-    const bool staged = (int64_t)hw * hh + (int64_t)vwd * vh <= cap;
-    float *hb = s_band, *vb = s_band + (staged ? hw * hh : 0);
+    const int hrows = VB ? hh : hh + 7;  // without V, column words read whole chunks of 8 rows of H
+    const bool staged = (int64_t)hw * hrows + (VB ? (int64_t)vwd * vh : 0) <= cap;
+    float *hb = s_band, *vb = s_band + (staged ? hw * hrows : 0);
     if (staged) {
         {
-            const int area = hw * hh;
+            const int area = hw * hrows;
             int y = t / hw, x = t % hw;
             const int dy = kRpcfT / hw, dx = kRpcfT % hw;
             for (int idx = t; idx < area; idx += kRpcfT) {
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
                 }
             }
         }
-        {
+        if (VB) {
             // read row by row (coalesced), store transposed
             const int area = vwd * vh;
             int y = t / vwd, x = t % vwd;
@@ -292,8 +297,13 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     auto colword = [&](int i) -> uint64_t {
         if (!valid) return 0ull;
         if (staged) {
-            const lds_float *line = vbl + (i - vx) * vh + (A.j0 - r - 1 - vy);
-            return shadow_bits([&](int q) { return line[q]; }, nbc, A.zb);
+            if constexpr (VB) {
+                const lds_float *line = vbl + (i - vx) * vh + (A.j0 - r - 1 - vy);
+                return shadow_bits([&](int q) { return line[q]; }, nbc, A.zb);
+            } else {
+                const lds_float *col = hbl + (A.j0 - r - 1 - hy) * hw + (i - hx);
+                return shadow_bits([&](int q) { return col[q * hw]; }, nbc, A.zb);
+            }
         }
         const int j = A.j0 - r - 1;
         return shadow_bits([&](int q) { return canon(texel(m, i, j + q)); }, nbc, A.zb);
@@ -371,15 +381,21 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
                 if (staged) {
                     // H: rows j, j+1 (top), j-1 (bottom) along columns;
                     // V: columns i, i-1 (left), i+1 (right) along rows
-                    const lds_float *ph = hbl + (j - hy) * hw, *pv = vbl + (i - vx) * vh;
+                    // (without V: H down column i, the side columns at -+1)
+                    const lds_float *ph = hbl + (j - hy) * hw;
+                    const lds_float *pv = VB ? vbl + (i - vx) * vh : hbl + (i - hx);
+                    const int vside = VB ? vh : 1;
                     BandWalkReader bh, bv;
                     bh.c = (lds_byte *)ph;
                     bh.a = (lds_byte *)(ph + hw);
                     bh.b = (lds_byte *)(ph - hw);
+                    bh.step = 4u;
                     bv.c = (lds_byte *)pv;
-                    bv.a = (lds_byte *)(pv - vh);
-                    bv.b = (lds_byte *)(pv + vh);
-                    const int ph0 = i - hx, pv0 = j - vy;
+                    bv.a = (lds_byte *)(pv - vside);
+                    bv.b = (lds_byte *)(pv + vside);
+                    bv.step = VB ? 4u : 4u * (unsigned)hw;
+                    const int ph0 = i - hx, pv0 = VB ? j - vy : j - hy;
+                    const int vlen = VB ? vh : hrows;  // band positions of a vertical traversal
                     const bool ht = (mk & BIT_T) != 0, hbt = (mk & BIT_B) != 0;
                     const bool vl = (mk & BIT_L) != 0, vr = (mk & BIT_R) != 0;
                     rd[0] = first_steps(bh, ph0, -1, maxd, zb, s, ht, hbt);
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
                         const int p0 = horiz ? ph0 : pv0;
                         const bool ca = horiz ? ht : vl, cb = horiz ? hbt : vr;
                         // last step inside the band
-                        const int kl = min(maxd, d > 0 ? (horiz ? hw : vh) - 1 - p0 : p0);
+                        const int kl = min(maxd, d > 0 ? (horiz ? hw : vlen) - 1 - p0 : p0);
                         int x = 0;
                         if (k0[dir] <= kl)
                             x = walk_range<4>(horiz ? bh : bv, k0[dir], kl, p0, d, INT32_MAX / 4, zb, s, ca, cb);
@@ -434,12 +450,20 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
     if (valid) out[k] = (float)(acc / (double)((2 * r + 1) * (2 * r + 1)));
 }
 
+// Radii up to this one stage the transposed band V (faster column words);
+// larger ones only H (half the LDS, more workgroups per CU).  Measured on the
+// 4K fenced frame, with V / without: r = 5 1.19 / 1.46 ms, 9 3.77 / 4.28,
+// 10 4.98 / 4.89, 13 8.43 / 7.25, 15 10.5 / 9.23.
+constexpr int kRpcfTransposedMaxR = 9;
+
 // LDS texels for the staged bands of an RPCF workgroup: enough for a tile
 // whose texel footprint spans up to 13 x 17 texels, within 64 KiB with the
 // kernel's static LDS.
 inline int rpcf_cap(int r, int maxd) {
     const int R = r + (maxd < kRpcfReach ? maxd : kRpcfReach);
-    const int want = (12 + 2 * R + 1) * (16 + 2 * r + 3) + (12 + 2 * r + 3) * ((16 + 2 * R + 1 + 7) | 1);
+    const int want = r <= kRpcfTransposedMaxR
+                         ? (12 + 2 * R + 1) * (16 + 2 * r + 3) + (12 + 2 * r + 3) * ((16 + 2 * R + 1 + 7) | 1)
+                         : (12 + 2 * R + 1) * (16 + 2 * r + 3 + 7);
     const int room = (65536 - 12288) / 4;
     return want < room ? want : room;
 }
@@ -458,12 +482,20 @@ inline void launch_rpcf(const MapView &mv, const float *frags, int64_t n, int64_
         const int64_t rows = (n + view_width - 1) / view_width;
         const int64_t tiles_x = (view_width + TW - 1) / TW;
         const int64_t tiles = tiles_x * ((rows + TH - 1) / TH);
-        hipLaunchKernelGGL((rpcf_kernel<TW>), dim3((unsigned)tiles), dim3(kRpcfT), lds, stream, mv, frags, n,
-                           view_width, tiles_x, bias, maxd, r, cap, out);
+        if (r <= kRpcfTransposedMaxR)
+            hipLaunchKernelGGL((rpcf_kernel<TW, true>), dim3((unsigned)tiles), dim3(kRpcfT), lds, stream, mv, frags,
+                               n, view_width, tiles_x, bias, maxd, r, cap, out);
+        else
+            hipLaunchKernelGGL((rpcf_kernel<TW, false>), dim3((unsigned)tiles), dim3(kRpcfT), lds, stream, mv, frags,
+                               n, view_width, tiles_x, bias, maxd, r, cap, out);
     } else {
         const int64_t tiles = (n + kRpcfT - 1) / kRpcfT;
-        hipLaunchKernelGGL((rpcf_kernel<kRpcfT>), dim3((unsigned)tiles), dim3(kRpcfT), lds, stream, mv, frags, n,
-                           n, tiles, bias, maxd, r, cap, out);
+        if (r <= kRpcfTransposedMaxR)
+            hipLaunchKernelGGL((rpcf_kernel<kRpcfT, true>), dim3((unsigned)tiles), dim3(kRpcfT), lds, stream, mv,
+                               frags, n, n, tiles, bias, maxd, r, cap, out);
+        else
+            hipLaunchKernelGGL((rpcf_kernel<kRpcfT, false>), dim3((unsigned)tiles), dim3(kRpcfT), lds, stream, mv,
+                               frags, n, n, tiles, bias, maxd, r, cap, out);
     }
 }
 

@@ -92,10 +92,11 @@ def test_rpcf_full_size_sampled(rb):
     check_soft(c["map"], c["frags"], p, got, idx)
 
 
-@pytest.mark.parametrize("r,max_dist", [(1, 1), (1, 16), (3, 16), (7, 16), (15, 16), (2, 29), (30, 1),
-                                        (2, 40), (6, 64), (31, 4), (32, 2)])
+@pytest.mark.parametrize("r,max_dist", [(1, 1), (1, 16), (3, 16), (7, 16), (9, 16), (10, 16), (12, 64), (15, 16),
+                                        (2, 29), (30, 1), (2, 40), (6, 64), (31, 4), (32, 2)])
 def test_rpcf_radii_and_reach(rb, r, max_dist):
-    """Every RPCF route: staged bands (screen tiles), reads from global memory
+    """Every RPCF route: staged bands (screen tiles; up to r = 9 with the
+    transposed band, beyond it the row band alone), reads from global memory
     (bands too large), and the per-term form when a column of 2r+3 rows no
     longer fits one word (r > 30)."""
     c = synth.make_config(3, 3005, small=True)
@@ -126,7 +127,7 @@ def test_rpcf_clamped_edges_of_tiny_maps(rb):
     for (H, W) in [(1, 1), (3, 2), (9, 17), (40, 33)]:
         m = np.where(rng.random((H, W)) < 0.4, 0.5, 0.9).astype(np.float32)
         f = _frags_for(W, H, 3000 + W, seed=W, spill=0.2)
-        for r, vw in ((2, 0), (5, 50)):
+        for r, vw in ((2, 0), (5, 50), (11, 50)):
             p = dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=12, kernel_radius=r, view_width=vw)
             got = rb.rsmss_visibility(dev(m), dev(f), p).cpu().numpy()
             check_soft(m, f, p, got)
@@ -223,7 +224,7 @@ def test_rpcf_long_traversals_leave_the_staged_band(rb, name):
     H, W = m.shape
     f = _screen_frags(W, H, 160, 120, seed=H + len(name))
     md, fd = dev(m), dev(f)
-    for r, max_dist in ((2, 40), (5, 64), (3, 9), (1, 63)):
+    for r, max_dist in ((2, 40), (5, 64), (3, 9), (1, 63), (11, 40)):
         say(f"rpcf long {name} r={r} maxd={max_dist}")
         p = dict(width=W, height=H, pitch=W, depth_bias=1e-4, max_dist=max_dist, kernel_radius=r, view_width=160)
         got = rb.rsmss_visibility(md, fd, p).cpu().numpy()
