@@ -196,9 +196,10 @@ __device__ __forceinline__ int column_walk_down(uint64_t wl, uint64_t w, uint64_
 // workgroups per CU, for slower column reads and a shorter vertical reach.
 // Band coordinates are unclamped positions holding clamped texels, so no read
 // clamps.  Otherwise everything reads global memory.  Requires 1 <= r <=
-// kRpcfMaxR.
+// kRpcfMaxR.  At most 128 VGPRs (4 waves per SIMD): the H-only form would
+// take 154 (3 waves) and runs 5-12% faster held to 128, a few values spilled.
 template <int TW, bool VB>
-__global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__restrict__ frags, int64_t n,
+__global__ __launch_bounds__(kRpcfT) __attribute__((amdgpu_waves_per_eu(4))) void rpcf_kernel(MapView m, const float *__restrict__ frags, int64_t n,
                                                       int64_t vw, int64_t tiles_x, float bias, int maxd, int r,
                                                       int cap, float *__restrict__ out) {
     extern __shared__ float s_band[];
@@ -453,7 +454,9 @@ __global__ __launch_bounds__(kRpcfT) void rpcf_kernel(MapView m, const float *__
 // Radii up to this one stage the transposed band V (faster column words);
 // larger ones only H (half the LDS, more workgroups per CU).  Measured on the
 // 4K fenced frame, with V / without: r = 5 1.19 / 1.46 ms, 9 3.77 / 4.28,
-// 10 4.98 / 4.89, 13 8.43 / 7.25, 15 10.5 / 9.23.
+// 10 4.98 / 4.89, 13 8.43 / 7.25, 15 10.5 / 9.23 (before the kernel was held
+// to 128 VGPRs, which brought the H-only form to 4.32 / 6.38 / 8.78 ms at
+// r = 10 / 13 / 15).
 constexpr int kRpcfTransposedMaxR = 9;
 
 // LDS texels for the staged bands of an RPCF workgroup: enough for a tile
