@@ -15,7 +15,8 @@
 // every lane busy instead of holding a wave for its busiest fragment.  A
 // vertical traversal is first resolved on the fragment's column words, which
 // hold the shadow-test bits of every row it can reach inside the kernel's
-// window; horizontal ones take their first two steps from a staged band.  The
+// window; horizontal ones take their first step from the neighbouring column's
+// word and their second from a staged band.  The
 // bands reach only a few steps past the window, which keeps the workgroup's
 // LDS small enough for more of them per CU; the few longer traversals go on
 // in global memory.
@@ -121,16 +122,19 @@ struct MapLineReader {
     }
 };
 
-// The first two steps of a traversal (Listing 3) from a staged band, with no
-// branches so that the reads of all four traversals of a term can be in
-// flight together: +k / -k for the first stopping step, 0 if neither stops.
-__device__ __forceinline__ int first_steps(const BandWalkReader &br, int p0, int d, int maxd, float zb, bool s,
-                                           bool chk_a, bool chk_b) {
-    float c1, a1, b1, c2, a2, b2;
-    br(p0 + d, c1, a1, b1);
+// The first two steps of a horizontal traversal (Listing 3), with no branches
+// so that the reads of all four traversals of a term can be in flight
+// together: step 1 from w1, the shadow-test word of the neighbouring column in
+// the walk's direction (bit q the term's row, q + 1 and q - 1 its side rows,
+// bit 1 = in shadow), step 2 from the staged band.  +k / -k for the first
+// stopping step, 0 if neither stops.
+__device__ __forceinline__ int first_steps(const BandWalkReader &br, uint64_t w1, int q, int p0, int d, int maxd,
+                                           float zb, bool s, bool chk_a, bool chk_b) {
+    float c2, a2, b2;
     br(p0 + (maxd >= 2 ? 2 * d : d), c2, a2, b2);
-    const bool end1 = (zb > c1) == s, end2 = (zb > c2) == s;
-    const bool share1 = (chk_a & ((zb > a1) == s)) | (chk_b & ((zb > b1) == s));
+    const uint64_t v = s ? w1 : ~w1;  // bit set: that texel's test differs from the term's
+    const bool end1 = (v >> q) & 1ull, end2 = (zb > c2) == s;
+    const bool share1 = (chk_a & (bool)((v >> (q + 1)) & 1ull)) | (chk_b & (bool)((v >> (q - 1)) & 1ull));
     const bool share2 = (chk_a & ((zb > a2) == s)) | (chk_b & ((zb > b2) == s));
     const int at2 = maxd >= 2 ? (end2 ? 2 : (share2 ? 0 : -2)) : 0;
     return end1 ? 1 : (share1 ? at2 : -1);
@@ -399,17 +403,17 @@ __global__ __launch_bounds__(kRpcfT) __attribute__((amdgpu_waves_per_eu(4))) voi
                     const int vlen = VB ? vh : hrows;  // band positions of a vertical traversal
                     const bool ht = (mk & BIT_T) != 0, hbt = (mk & BIT_B) != 0;
                     const bool vl = (mk & BIT_L) != 0, vr = (mk & BIT_R) != 0;
-                    rd[0] = first_steps(bh, ph0, -1, maxd, zb, s, ht, hbt);
-                    rd[1] = first_steps(bh, ph0, 1, maxd, zb, s, ht, hbt);
-                    // vertical traversals over the fragment's column words
-                    // (rows j0-r-1 .. j0+r+1) as far as they reach
+                    // the fragment's column words of the term's column and its
+                    // neighbours (rows j0-r-1 .. j0+r+1): the horizontal
+                    // traversals' first steps, and the vertical ones as far
+                    // as the words reach
+                    const int x = (en >> (LB + 11)) & 1u;
+                    const uint64_t wl = s_cw[x][L], w = s_cw[x + 1][L], wr = s_cw[x + 2][L];
+                    rd[0] = first_steps(bh, wl, q, ph0, -1, maxd, zb, s, ht, hbt);
+                    rd[1] = first_steps(bh, wr, q, ph0, 1, maxd, zb, s, ht, hbt);
                     int k0[4] = {3, 3, 0, 0};
-                    {
-                        const int x = (en >> (LB + 11)) & 1u;
-                        const uint64_t wl = s_cw[x][L], w = s_cw[x + 1][L], wr = s_cw[x + 2][L];
-                        rd[2] = column_walk_up(wl, w, wr, q, nbc, maxd, s, vl, vr, k0[2]);
-                        rd[3] = column_walk_down(wl, w, wr, q, maxd, s, vl, vr, k0[3]);
-                    }
+                    rd[2] = column_walk_up(wl, w, wr, q, nbc, maxd, s, vl, vr, k0[2]);
+                    rd[3] = column_walk_down(wl, w, wr, q, maxd, s, vl, vr, k0[3]);
                     // the few that run on
                     for (int dir = 0; dir < 4; ++dir) {
                         if (rd[dir] != 0) continue;
