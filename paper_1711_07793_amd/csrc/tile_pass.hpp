@@ -1135,13 +1135,87 @@ void launch_tiles(const MapView &mv, const float *frags, int64_t n, int64_t vw, 
 // so staging would not happen anyway.
 constexpr int64_t kFlatFragMax = (int64_t)1 << 20;
 
+// One fragment's visibility (Listing 1) with the reads of each round issued
+// together: its five texels, then the first two steps of all four walks
+// (24 reads); walks still running continue in blocks of 4 steps.  The same
+// texels and tests as eval_texel, whose walks take one dependent read per
+// step, one walk after the other.  Maps under 4 GiB (32-bit byte offsets).
+template <bool HARD>
+__device__ __forceinline__ float eval_texel_blocked(const MapView &m, const Addr &a, int maxd) {
+    const int i0 = a.i0, j0 = a.j0;
+    const float zb = a.zb;
+    const float t_c = texel(m, i0, j0), t_l = texel(m, i0 - 1, j0), t_r = texel(m, i0 + 1, j0);
+    const float t_t = texel(m, i0, j0 + 1), t_b = texel(m, i0, j0 - 1);
+    const bool s = lit(zb, t_c);
+    if (HARD && !s) return 0.0f;
+    const unsigned m0 = (lit(zb, t_l) != s ? BIT_L : 0u) | (lit(zb, t_r) != s ? BIT_R : 0u) |
+                        (lit(zb, t_t) != s ? BIT_T : 0u) | (lit(zb, t_b) != s ? BIT_B : 0u);
+    if (m0 == 0u) return s ? 1.0f : 0.0f;
+    // walks 0 left, 1 right, 2 top, 3 bottom: the moving coordinate p, and the
+    // fixed one of the walk's texel and its side neighbours (clamped)
+    GlobalWalkReader rw[4];
+    int p0[4], d[4], pmax[4];
+    bool ca[4], cb[4];
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir) {
+        const bool horiz = dir < 2;
+        d[dir] = dir == 0 || dir == 3 ? -1 : 1;
+        p0[dir] = horiz ? i0 : j0;
+        pmax[dir] = (horiz ? m.W : m.H) - 1;
+        ca[dir] = horiz ? (m0 & BIT_T) != 0 : (m0 & BIT_L) != 0;
+        cb[dir] = horiz ? (m0 & BIT_B) != 0 : (m0 & BIT_R) != 0;
+        const unsigned fmul = horiz ? 4u * (unsigned)m.pitch : 4u;
+        rw[dir].t = (const char *)m.t;
+        rw[dir].c = (unsigned)(horiz ? clampi(j0, m.H) : clampi(i0, m.W)) * fmul;
+        rw[dir].a = (unsigned)(horiz ? clampi(j0 + 1, m.H) : clampi(i0 - 1, m.W)) * fmul;
+        rw[dir].b = (unsigned)(horiz ? clampi(j0 - 1, m.H) : clampi(i0 + 1, m.W)) * fmul;
+        rw[dir].step4 = horiz ? 4u : 4u * (unsigned)m.pitch;
+    }
+    const int first = min(2, maxd);
+    float tc[4][2], ta[4][2], tb[4][2];
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int ku = min(1 + u, first);
+            rw[dir](min(max(p0[dir] + ku * d[dir], 0), pmax[dir]), tc[dir][u], ta[dir][u], tb[dir][u]);
+        }
+    int rd[4];
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir) {
+        // bit u: step 1 + u ends the walk, or stops it (as in walk_range)
+        unsigned endb = 0u, stopb = 0u;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const bool end = (zb > tc[dir][u]) == s;
+            const bool share = (ca[dir] & ((zb > ta[dir][u]) == s)) | (cb[dir] & ((zb > tb[dir][u]) == s));
+            endb |= (unsigned)end << u;
+            stopb |= (unsigned)(end | !share) << u;
+        }
+        stopb &= first >= 2 ? 3u : 1u;
+        const int u = __builtin_ctz(stopb | 4u);
+        rd[dir] = stopb != 0u ? ((endb >> u) & 1u ? 1 + u : -(1 + u)) : 0;
+    }
+#pragma unroll
+    for (int dir = 0; dir < 4; ++dir) {
+        if (rd[dir] == 0 && first < maxd)
+            rd[dir] = walk_range<4>(rw[dir], first + 1, maxd, p0[dir], d[dir], pmax[dir], zb, s, ca[dir], cb[dir]);
+        if (rd[dir] == 0) rd[dir] = -(maxd + 1);
+    }
+    const Axis ax = normalize_axis(rd[0], rd[1], a.fx);
+    const Axis ay = normalize_axis(rd[3], rd[2], a.fy);
+    return HARD ? vis_hard(ax, ay) : vis_rsmss(s, ax, ay);
+}
+
 template <bool HARD>
 __global__ __launch_bounds__(256) void frag_kernel(MapView m, const float *__restrict__ frags, int64_t n, float bias,
                                                    int maxd, void *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     const Addr a = address(gld(frags + 3 * k), gld(frags + 3 * k + 1), gld(frags + 3 * k + 2), m.W, m.H, bias);
-    const float v = eval_texel<HARD>(m, a.i0, a.j0, a.fx, a.fy, a.zb, maxd);
+    const bool map_32 = (int64_t)m.pitch * m.H * 4 <= (int64_t)0xFFFFFFFFu;  // byte offsets fit 32 bits
+    const float v = map_32 ? eval_texel_blocked<HARD>(m, a, maxd)
+                           : eval_texel<HARD>(m, a.i0, a.j0, a.fx, a.fy, a.zb, maxd);
     if (HARD) gst(static_cast<uint8_t *>(out) + k, (uint8_t)(v != 0.0f ? 1 : 0));
     else gst(static_cast<float *>(out) + k, v);
 }
