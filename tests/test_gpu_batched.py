@@ -339,3 +339,43 @@ def test_rpcf_jobs_in_the_plan(rb, workload):
     with pytest.raises(rb.RbsmError):
         plan.update(bad)
     plan.close()
+
+
+@pytest.mark.parametrize("copies", [1, 9], ids=["args", "tables"])
+def test_mixed_job_order_empty_and_rpcf_jobs(rb, copies):
+    """Jobs whose modes alternate, with empty jobs and RPCF jobs between them:
+    the plan launches the RSMSS jobs' tiles first, the allocation-free entry
+    point in job order; every output is bitwise the plain call's (one plan of
+    6 jobs, kernel-argument records; nine copies, 54 jobs, device tables)."""
+    c2 = synth.make_config(2, 2011, small=True)
+    c3 = synth.make_config(3, 3011, small=True)
+    m2, f2 = torch.from_numpy(c2["map"]).cuda(), torch.from_numpy(c2["frags"]).cuda()
+    m3, f3 = torch.from_numpy(c3["map"]).cuda(), torch.from_numpy(c3["frags"]).cuda()
+
+    def job(mode, m, f, params, n=None):
+        f = f if n is None else f[:n].contiguous()
+        out = torch.full((f.shape[0],), 7 if mode == 0 else -1.0,
+                         dtype=torch.uint8 if mode == 0 else torch.float32, device="cuda")
+        return dict(map=m, frags=f, params=params, mode=mode, out=out)
+
+    jobs = []
+    for _ in range(copies):
+        jobs += [job(0, m2, f2, c2["params"]),
+                 job(1, m3, f3, dict(c3["params"], kernel_radius=0), n=0),
+                 job(1, m3, f3, dict(c3["params"], kernel_radius=0)),
+                 job(1, m3, f3, dict(c3["params"], kernel_radius=2), n=5000),
+                 job(0, m2, f2, c2["params"], n=0),
+                 job(1, m2, f2, dict(c2["params"], kernel_radius=0), n=777)]
+    want = [_plain(rb, j) for j in jobs]
+    plan = rb.Plan(jobs)
+    plan.launch()
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        assert np.array_equal(j["out"].cpu().numpy(), want[k]), ("plan", k)
+    plan.close()
+    for j in jobs:
+        j["out"].fill_(3)
+    rb.batch_launch_noalloc(jobs)
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        assert np.array_equal(j["out"].cpu().numpy(), want[k]), ("noalloc", k)
